@@ -1,0 +1,186 @@
+/*
+ * ddf.h -- C ABI of the MI355X (gfx950) directed-distance-field hot path.
+ *
+ * A directed distance field (DDF) maps a ray, origin x in R^3 and unit
+ * direction d, to (t, xi): the distance from x along d to the first surface
+ * and the probability that the ray hits anything (paper Sec. III-A, Eq. 1).
+ * The field here is the sinusoidal-encoding MLP form (Sec. IV-C, Table II):
+ *
+ *   gamma(v) = [v, sin(pi 2^0 v), cos(pi 2^0 v), ..., sin(pi 2^(L-1) v), cos(pi 2^(L-1) v)]
+ *   h_1 = relu(W_1 gamma + b_1),  h_l = relu(W_l h_(l-1) + b_l)  (l = 2..n_hidden)
+ *   z   = W_head h_n + b_head,    t = softplus(z_0),  xi = sigmoid(z_1)
+ *
+ * Every query is one forward pass (Sec. III-C).  The same network shape with
+ * n_in = 3 and one linear output is the signed-distance MLP that the SDF
+ * sphere-tracing baseline evaluates once per step (Sec. IV-D, Table IV).
+ *
+ * Conventions for every entry point:
+ *  - Buffer pointers are DEVICE pointers owned by the caller, 16-byte
+ *    aligned.  Descriptors and hyper-parameters are host structs.  The
+ *    library never allocates, frees or synchronises; all work is enqueued
+ *    on `stream` (a hipStream_t passed as void*, NULL = the null stream).
+ *  - Arguments are validated on the host before anything is enqueued; on a
+ *    failure nothing is written, the call returns a negative ddf_status and
+ *    ddf_last_error() holds a message (thread-local).
+ *  - n == 0 is a valid no-op.
+ *  - Rays are float32 SoA [6][n]: rows x0, x1, x2, d0, d1, d2 (row stride n).
+ *    Directions are expected to be unit length; they are not renormalised.
+ *    A NaN in a ray only affects that ray's outputs.
+ *  - The float32 master parameter vector is flat: for each hidden layer
+ *    W_l [width][fan_in] row-major then b_l [width]; then W_head
+ *    [n_out][width] and b_head [n_out].  fan_in of layer 1 is
+ *    n_in (1 + 2 n_freq).
+ */
+#ifndef DDF_H_
+#define DDF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DDF_OK = 0,
+  DDF_ERR_INVALID_ARG = -1,  /* bad pointer, size, descriptor field or alignment */
+  DDF_ERR_UNSUPPORTED = -2,  /* valid but not built: width/precision combination */
+  DDF_ERR_WORKSPACE = -3,    /* workspace smaller than the sizing call returned */
+  DDF_ERR_HIP = -4           /* a HIP launch or runtime call failed */
+} ddf_status;
+
+typedef enum {
+  DDF_FP32 = 0,      /* float32 operands on the fp32 matrix cores */
+  DDF_BF16 = 1,      /* bf16 operands, fp32 accumulation */
+  DDF_FP8_E4M3 = 2   /* OCP e4m3 hidden layers with per-layer power-of-two scales */
+} ddf_precision;
+
+typedef struct {
+  int32_t n_in;       /* 6 = DDF ray (x, d); 3 = SDF point p */
+  int32_t n_freq;     /* L, frequency bands of the encoding (1..12) */
+  int32_t n_hidden;   /* Linear+ReLU layers, 1..32; the first maps the features to width */
+  int32_t width;      /* 128, 256, 512 or 1024 */
+  int32_t n_out;      /* 2 = (z_t, z_xi) for a DDF; 1 = signed distance */
+  int32_t precision;  /* ddf_precision of the hidden-layer products */
+} ddf_net_desc;
+
+/* Human-readable name of a status code; static storage. */
+const char* ddf_status_string(int status);
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* ddf_last_error(void);
+
+/* Length of the float32 master parameter vector (layout above); 0 if desc is invalid. */
+size_t ddf_param_count(const ddf_net_desc* desc);
+
+/* Bytes of the packed working copy of the network for desc->precision; 0 if invalid.
+ * The packed form is opaque: weights pre-arranged in matrix-core operand order,
+ * fp32 biases and heads, and (FP8) the per-layer scales. */
+size_t ddf_packed_bytes(const ddf_net_desc* desc);
+
+/* Build the packed working copy from the float32 master.
+ *   master      device, ddf_param_count floats, read only.
+ *   act_scales  host, FP8 only (else may be NULL): n_hidden - 1 power-of-two scales
+ *               s_A of the inputs of hidden layers 2..n_hidden (an input h is stored as
+ *               e4m3(h / s_A)); see ddf_fp8_act_scales.
+ *   packed      device, ddf_packed_bytes bytes, written.
+ * FP8 weight scales are computed here, per hidden layer l >= 2, as the smallest power of
+ * two s_W with max|W_l| / s_W <= 448.  Layer 1 stays bf16 (hi + lo split input) and the
+ * heads fp32 in every reduced precision. */
+int ddf_pack(const ddf_net_desc* desc, const float* master, const float* act_scales,
+             void* packed, void* stream);
+
+/* The batched DDF query (Sec. III-A Eq. 1, Sec. III-C): one forward pass per ray.
+ *   packed  device, from ddf_pack with the same desc.
+ *   rays    device float32 [6][n] SoA.
+ *   t, xi   device float32 [n]: t = softplus(z_t) >= 0, xi = sigmoid(z_xi) in [0, 1].
+ * desc->n_in must be 6 and desc->n_out 2. */
+int ddf_query(const ddf_net_desc* desc, const void* packed, const float* rays, int64_t n,
+              float* t, float* xi, void* stream);
+
+/* Per-layer power-of-two FP8 input scales from a calibration batch (host result).
+ * Runs the float32 forward of `master` (desc with precision DDF_FP32 semantics) over
+ * `rays` [6][n] and returns in act_scales_host[0 .. n_hidden-2] the smallest power of
+ * two s with max(h_(l-1)) / s <= 448 for l = 2..n_hidden.  Synchronises `stream`.
+ *   packed_fp32  device, ddf_packed_bytes of desc with precision DDF_FP32, from ddf_pack.
+ *   ws           device workspace, ddf_fp8_calib_workspace_bytes(desc, n) bytes. */
+size_t ddf_fp8_calib_workspace_bytes(const ddf_net_desc* desc, int64_t n);
+int ddf_fp8_act_scales(const ddf_net_desc* desc, const void* packed_fp32, const float* rays,
+                       int64_t n, float* act_scales_host, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* ------------------------------------------------------------------ training */
+
+typedef struct {
+  float lr;            /* learning rate of this step (the caller applies the schedule) */
+  float beta1, beta2;  /* Adam moments, e.g. 0.9, 0.999 */
+  float eps;           /* Adam epsilon, e.g. 1e-8 */
+  float bce_weight;    /* weight of the hit cross-entropy, 0.3 (Sec. III-D) */
+  float l1_clamp;      /* clamp of the per-ray L1 distance error, e.g. 3.0 (box scale) */
+  int64_t step;        /* 1-based Adam step count (bias correction) */
+} ddf_train_hparams;
+
+/* Workspace for one training step / backward pass over `batch` rays. */
+size_t ddf_train_workspace_bytes(const ddf_net_desc* desc, int64_t batch);
+
+/* Training-mode forward: z_t and z_xi logits per ray [n], and the activations the
+ * backward pass needs kept in `ws`.  Same numerics as ddf_query. */
+int ddf_forward_train(const ddf_net_desc* desc, const void* packed, const float* rays,
+                      int64_t n, float* z_t, float* z_xi, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/* Backward pass of the network for given logit gradients (dL/dz_t, dL/dz_xi), each
+ * device float32 [n]; must follow ddf_forward_train on the same rays and ws.  Writes the
+ * float32 gradient of every parameter (master layout) to grad_params (device). */
+int ddf_backward(const ddf_net_desc* desc, const void* packed, const float* rays, int64_t n,
+                 const float* grad_z_t, const float* grad_z_xi, float* grad_params,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* One distillation step (Sec. III-B, III-D): forward, loss, backward, Adam, repack.
+ *   loss = mean over hit rays of min(|softplus(z_t) - t_gt|, l1_clamp)
+ *        + bce_weight * mean over all rays of BCE(sigmoid(z_xi), hit_gt)
+ *   master, adam_m, adam_v   device float32 [ddf_param_count], updated in place.
+ *   packed                   device, rebuilt from the new master (FP8 keeps its
+ *                            activation scales).
+ *   t_gt                     device float32 [batch], ignored where hit_gt == 0.
+ *   hit_gt                   device uint8 [batch], 0 or 1.
+ *   loss_out                 device float32 [3]: total, l1 term, bce term.
+ *   nonfinite_flag           device int32 [1]: set to 1 and the update skipped (master,
+ *                            m, v untouched) when any gradient is not finite, else 0.
+ *   grad_out                 device float32 [ddf_param_count] or NULL: the gradient. */
+int ddf_train_step(const ddf_net_desc* desc, float* master, float* adam_m, float* adam_v,
+                   void* packed, const float* rays, const float* t_gt, const uint8_t* hit_gt,
+                   int64_t batch, const ddf_train_hparams* hp, float* loss_out,
+                   int32_t* nonfinite_flag, float* grad_out, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* ------------------------------------------------------------------ baselines / data */
+
+/* Sphere tracing of an SDF MLP (the baseline of Sec. IV-D, Table IV): per ray, from
+ * t = 0, evaluate s = sdf(x + t d); |s| < hit_eps is a hit, else t += s; t > t_max is a
+ * miss; max_steps evaluations without either is a miss that did not converge.
+ *   desc    n_in 3, n_out 1.   packed from ddf_pack.   rays [6][n].
+ *   t       device float32 [n], final t.   hit device uint8 [n].
+ *   steps   device int32 [n] or NULL: SDF evaluations used by each ray.
+ *   ws      sdf_trace_workspace_bytes(n) bytes. */
+size_t sdf_trace_workspace_bytes(int64_t n);
+int sdf_sphere_trace(const ddf_net_desc* desc, const void* packed, const float* rays,
+                     int64_t n, int32_t max_steps, float hit_eps, float t_max, float* t,
+                     uint8_t* hit, int32_t* steps, void* ws, size_t ws_bytes, void* stream);
+
+/* Signed-distance MLP at points: sdf [n] for points float32 SoA [3][n]. */
+int sdf_eval(const ddf_net_desc* desc, const void* packed, const float* points, int64_t n,
+             float* sdf, void* stream);
+
+/* Exact supervision targets by brute-force ray casting against an analytic union of
+ * spheres/ellipsoids (the paper's exact ray-cast supervision source, Sec. III-B).
+ *   prims  device float32 [n_prims][16]: center(3), 1/semi-axes(3), R^T row-major(9),
+ *          unused(1), where a primitive is {c + R (a * u) : |u| <= 1}.
+ *   t_gt   device float32 [n]: first root > 0 over all primitives (+inf on a miss).
+ *   hit    device uint8 [n]. */
+int ddf_cast_targets(const float* prims, int32_t n_prims, const float* rays, int64_t n,
+                     float* t_gt, uint8_t* hit, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DDF_H_ */

@@ -1,0 +1,322 @@
+// Fused forward pass of the DDF / SDF MLP on the gfx950 matrix cores.
+//
+// One workgroup (4 waves, one per SIMD) owns a tile of M rays for the whole
+// network.  The tile's activations stay in LDS ([M][width] in the operand
+// type) for all layers; each wave owns width/4 output neurons and streams
+// the matching pre-arranged weight blocks straight from global memory into
+// registers (every weight element is read once per workgroup and used for
+// all M rays).  Products run on MFMA with fp32 accumulation:
+//   fp32: v_mfma_f32_32x32x2_f32, M = 32
+//   bf16: v_mfma_f32_32x32x16_bf16, M = 64
+// The epilogue adds the bias, applies ReLU, rounds to the next layer's
+// operand type and writes the tile back into LDS.  The last layer feeds the
+// two fp32 heads directly from the accumulators (cross-lane and cross-wave
+// reductions in a fixed order), so the heads always read the unrounded last
+// hidden layer.  The sinusoidal encoding is computed in registers into LDS
+// at the start of the tile; it never touches HBM.
+#include "ddf_internal.h"
+#include "ddf_fwd.h"
+
+namespace ddf {
+
+struct PF32 {
+  using E = float;
+  using AFrag = f32x4;
+  using BFrag = f32x4;
+  static constexpr int M = 32;
+  static constexpr int KBLK = 8;
+  static constexpr int PF = 1;       // weight blocks in flight ahead of the one in use
+  static __device__ inline void mma(f32x16& c, const AFrag& a, const BFrag& b) {
+    // k is permuted inside the block: step s uses k = 4 * (lane / 32) + s
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b[3], c, 0, 0, 0);
+  }
+};
+
+struct PBF16 {
+  using E = __bf16;
+  using AFrag = bf16x8;
+  using BFrag = bf16x8;
+  static constexpr int M = 64;
+  static constexpr int KBLK = 16;
+  static constexpr int PF = 1;
+  static __device__ inline void mma(f32x16& c, const AFrag& a, const BFrag& b) {
+    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class P, int WIDTH>
+struct Chain {
+  using E = typename P::E;
+  using AFrag = typename P::AFrag;
+  using BFrag = typename P::BFrag;
+  static constexpr int M = P::M;
+  static constexpr int RT = M / 32;                  // 32-ray tiles per workgroup
+  static constexpr int NT = WIDTH / 32 / kWaves;     // 32-neuron tiles per wave
+  static constexpr int LDX = WIDTH + 16 / (int)sizeof(E);  // padded LDS row (elements)
+  static constexpr int PF = P::PF;
+
+  static __device__ inline BFrag load_b(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+    return __builtin_bit_cast(BFrag, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
+  }
+
+  // acc[rt][t] += X[rt rows][0:K] * W[(nt0 + t) neuron tile][0:K]^T.  The weight blocks of
+  // one layer are read through a buffer resource: per-lane offset lane * 16 bytes, the
+  // block offset ((nt0 + t) KB + k) * 1 KiB is wave-uniform.  KB is even; the loads run
+  // one block ahead, and the one past the end of the layer is bounds-checked by the
+  // buffer resource (it returns zeros and is never used).
+  static __device__ inline void gemm(f32x16 (&acc)[RT][NT], const E* X, const void* W, int KB,
+                                     int nt0, int lane) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, WIDTH * KB * 32, 0x00020000);
+    const int voff = lane * 16;
+    const E* xrow = X + (lane & 31) * LDX + (P::KBLK / 2) * (lane >> 5);
+    BFrag b0[NT], b1[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) b0[t] = load_b(rs, voff, ((nt0 + t) * KB) * 1024);
+    for (int k = 0; k < KB; k += 2) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b1[t] = load_b(rs, voff, ((nt0 + t) * KB + k + 1) * 1024);
+      step(acc, xrow, k, b0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b0[t] = load_b(rs, voff, ((nt0 + t) * KB + k + 2) * 1024);
+      step(acc, xrow, k + 1, b1);
+    }
+  }
+
+  static __device__ inline void step(f32x16 (&acc)[RT][NT], const E* xrow, int k, const BFrag (&b)[NT]) {
+    AFrag av[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+      av[rt] = *reinterpret_cast<const AFrag*>(xrow + rt * 32 * LDX + k * P::KBLK);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) P::mma(acc[rt][t], av[rt], b[t]);
+  }
+};
+
+// Row of the 32x32 accumulator held in register v by `lane`.
+__device__ inline int acc_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+// Encoded inputs of rays [ray0, ray0 + M) into X[:, 0:k1]; padding columns are zero.
+// Reduced precisions store the bf16 hi part in columns [0, k1_half) and the lo part
+// in [k1_half, k1).  Train mode also writes the features (fp32, or bf16 hi) to slab 0
+// of the activation store, layout [rows / 8][k1_half][8].
+template <class E, int M, int LDX, int MODE>
+__device__ void encode_tile(const FwdArgs& a, int64_t ray0, E* X) {
+  const int n_in = a.n_in, nf = a.n_freq;
+  const int khalf = a.lay.k1_half;
+  const bool split = sizeof(E) == 2;
+  const int items = M * n_in * (1 + nf);
+  for (int idx = threadIdx.x; idx < items; idx += kThreads) {
+    const int r = idx % M;
+    const int rest = idx / M;
+    const int j = rest % n_in;
+    const int kk = rest / n_in;
+    const int64_t g = ray0 + r;
+    float v = 0.f;
+    if (g < a.n) {
+      if (MODE == kModeTrace) {
+        const int32_t src = a.idx[g];
+        const float tt = a.t_state[src];
+        v = fmaf(tt, a.in[(int64_t)(3 + j) * a.stride + src], a.in[(int64_t)j * a.stride + src]);
+      } else {
+        v = a.in[(int64_t)j * a.stride + g];
+      }
+    }
+    float f0, f1 = 0.f;
+    int c0, c1 = -1;
+    if (kk == 0) {
+      f0 = v; c0 = j;
+    } else {
+      sincospif(ldexpf(v, kk - 1), &f0, &f1);
+      c0 = (2 * kk - 1) * n_in + j;
+      c1 = c0 + n_in;
+    }
+    for (int w = 0; w < 2; ++w) {
+      const int c = w == 0 ? c0 : c1;
+      if (c < 0) break;
+      const float f = w == 0 ? f0 : f1;
+      if (split) {
+        const E hi = (E)f;
+        const E lo = (E)(f - (float)hi);
+        X[r * LDX + c] = hi;
+        X[r * LDX + khalf + c] = lo;
+      } else {
+        X[r * LDX + c] = (E)f;
+      }
+      if (MODE == kModeTrain)
+        reinterpret_cast<E*>(a.act)[((g >> 3) * khalf + c) * 8 + (g & 7)] = (E)f;
+    }
+  }
+  const int pad = khalf - a.lay.n_feat;
+  for (int idx = threadIdx.x; idx < M * pad; idx += kThreads) {
+    const int r = idx % M, c = a.lay.n_feat + idx / M;
+    X[r * LDX + c] = (E)0.f;
+    if (split) X[r * LDX + khalf + c] = (E)0.f;
+    if (MODE == kModeTrain) {
+      const int64_t g = ray0 + r;
+      reinterpret_cast<E*>(a.act)[((g >> 3) * khalf + c) * 8 + (g & 7)] = (E)0.f;
+    }
+  }
+}
+
+template <class P, int WIDTH, int MODE>
+__global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
+  using C = Chain<P, WIDTH>;
+  using E = typename P::E;
+  constexpr int M = C::M, RT = C::RT, NT = C::NT, LDX = C::LDX;
+  __shared__ __attribute__((aligned(16))) E X[M * LDX];
+  __shared__ float headp[kWaves][M][2];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+  const int64_t ray0 = (int64_t)blockIdx.x * M;
+  if (MODE == kModeTrace && ray0 >= *a.count) return;   // uniform: no active rays left here
+  const int64_t n_act = MODE == kModeTrace ? (int64_t)*a.count : a.n;
+  FwdArgs aa = a;
+  aa.n = n_act;
+
+  encode_tile<E, M, LDX, MODE>(aa, ray0, X);
+  __syncthreads();
+
+  const float* bias_all = reinterpret_cast<const float*>(a.packed + a.lay.b_off);
+  const float* hw = reinterpret_cast<const float*>(a.packed + a.lay.head_w_off);
+  const float* hb = reinterpret_cast<const float*>(a.packed + a.lay.head_b_off);
+  const int nt0 = wave * NT;
+
+  for (int l = 0; l < a.n_hidden; ++l) {
+    const int K = l == 0 ? a.lay.k1 : WIDTH;
+    const void* W = a.packed + a.lay.w_off[l];
+    f32x16 acc[RT][NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
+    C::gemm(acc, X, W, K / P::KBLK, nt0, lane);
+    __syncthreads();   // every wave is done reading X
+
+    const float* bias = bias_all + (int64_t)l * WIDTH;
+    const bool last = (l + 1 == a.n_hidden);
+    E* slab = MODE == kModeTrain
+                  ? reinterpret_cast<E*>(a.act) + (int64_t)a.lay.k1_half * a.act_rows +
+                        (int64_t)l * WIDTH * a.act_rows
+                  : nullptr;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      float hp0[16], hp1[16];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) { hp0[v] = 0.f; hp1[v] = 0.f; }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int n = (nt0 + t) * 32 + (lane & 31);
+        const float bv = bias[n];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[rt][t][v] = fmaxf(acc[rt][t][v] + bv, 0.f);
+        if (last) {
+          const float w0 = hw[n];
+          const float w1 = a.n_out > 1 ? hw[WIDTH + n] : 0.f;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            hp0[v] = fmaf(w0, acc[rt][t][v], hp0[v]);
+            hp1[v] = fmaf(w1, acc[rt][t][v], hp1[v]);
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) X[(rt * 32 + acc_row(v, lane)) * LDX + n] = (E)acc[rt][t][v];
+        }
+        if (slab) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t g0 = ray0 + rt * 32 + 8 * q;   // 8-ray block of registers 4q..4q+3
+            E* dst = slab + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5);
+            dst[0] = (E)acc[rt][t][4 * q + 0];
+            dst[1] = (E)acc[rt][t][4 * q + 1];
+            dst[2] = (E)acc[rt][t][4 * q + 2];
+            dst[3] = (E)acc[rt][t][4 * q + 3];
+          }
+        }
+      }
+      if (last) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          hp0[v] = wave_sum32(hp0[v]);
+          hp1[v] = wave_sum32(hp1[v]);
+        }
+        if ((lane & 31) == 0) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int r = rt * 32 + acc_row(v, lane);
+            headp[wave][r][0] = hp0[v];
+            headp[wave][r][1] = hp1[v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  for (int r = threadIdx.x; r < M; r += kThreads) {
+    const int64_t g = ray0 + r;
+    if (g >= n_act) continue;
+    float z0 = hb[0], z1 = a.n_out > 1 ? hb[1] : 0.f;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) { z0 += headp[w][r][0]; z1 += headp[w][r][1]; }
+    switch (MODE) {
+      case kModeQuery:
+        a.out0[g] = softplusf_(z0);
+        a.out1[g] = sigmoidf_(z1);
+        break;
+      case kModeTrain:
+        a.out0[g] = z0;
+        a.out1[g] = z1;
+        break;
+      case kModeSdf:
+        a.out0[g] = z0;
+        break;
+      default:
+        trace_update(a, a.idx[g], z0);
+        break;
+    }
+  }
+}
+
+template <class P, int WIDTH>
+static hipError_t launch_t(const FwdArgs& a, int64_t n_tiles, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  const dim3 grid((unsigned)n_tiles), block(kThreads);
+  switch (a.mode) {
+    case kModeQuery: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeQuery>), grid, block, 0, st, a); break;
+    case kModeTrain: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrain>), grid, block, 0, st, a); break;
+    case kModeSdf: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeSdf>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrace>), grid, block, 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(const ddf_net_desc& d, const FwdArgs& a, int64_t n_items,
+                          hipStream_t st) {
+  const Geo g = geo_of(d.precision);
+  const int64_t tiles = (n_items + g.rays_per_wg - 1) / g.rays_per_wg;
+  if (d.precision == DDF_FP32) {
+    switch (d.width) {
+      case 128: return launch_t<PF32, 128>(a, tiles, st);
+      case 256: return launch_t<PF32, 256>(a, tiles, st);
+      case 512: return launch_t<PF32, 512>(a, tiles, st);
+      case 1024: return launch_t<PF32, 1024>(a, tiles, st);
+    }
+  } else if (d.precision == DDF_BF16) {
+    switch (d.width) {
+      case 128: return launch_t<PBF16, 128>(a, tiles, st);
+      case 256: return launch_t<PBF16, 256>(a, tiles, st);
+      case 512: return launch_t<PBF16, 512>(a, tiles, st);
+      case 1024: return launch_t<PBF16, 1024>(a, tiles, st);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ddf

@@ -1,0 +1,246 @@
+"""Thin Python binding of libddf (include/ddf.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module only checks tensor
+placement/dtypes, allocates outputs with PyTorch (device memory and streams
+are PyTorch's job here) and forwards raw pointers plus the current HIP stream.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libddf.so")
+
+FP32, BF16, FP8 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
+
+
+class DDFError(RuntimeError):
+    pass
+
+
+class NetDescC(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_freq", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("n_out", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class TrainHParamsC(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("bce_weight", ctypes.c_float), ("l1_clamp", ctypes.c_float),
+                ("step", ctypes.c_int64)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+_D = ctypes.POINTER(NetDescC)
+
+SIGNATURES = {
+    "ddf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "ddf_last_error": (ctypes.c_char_p, []),
+    "ddf_param_count": (_SZ, [_D]),
+    "ddf_packed_bytes": (_SZ, [_D]),
+    "ddf_pack": (ctypes.c_int, [_D, _P, ctypes.POINTER(ctypes.c_float), _P, _P]),
+    "ddf_query": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, _P]),
+    "ddf_fp8_calib_workspace_bytes": (_SZ, [_D, _I64]),
+    "ddf_fp8_act_scales": (ctypes.c_int, [_D, _P, _P, _I64, ctypes.POINTER(ctypes.c_float), _P, _SZ, _P]),
+    "ddf_train_workspace_bytes": (_SZ, [_D, _I64]),
+    "ddf_forward_train": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, _P, _SZ, _P]),
+    "ddf_backward": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "ddf_train_step": (ctypes.c_int, [_D, _P, _P, _P, _P, _P, _P, _P, _I64, ctypes.POINTER(TrainHParamsC),
+                                      _P, _P, _P, _P, _SZ, _P]),
+    "sdf_trace_workspace_bytes": (_SZ, [_I64]),
+    "sdf_sphere_trace": (ctypes.c_int, [_D, _P, _P, _I64, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                        _P, _P, _P, _P, _SZ, _P]),
+    "sdf_eval": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P]),
+    "ddf_cast_targets": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P, _P, _P]),
+}
+
+
+def lib():
+    """The loaded libddf (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DDFError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python paper_2606_00817_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        L = lib()
+        raise DDFError(f"{L.ddf_status_string(rc).decode()}: {L.ddf_last_error().decode()}")
+
+
+def desc_c(desc, precision=None) -> NetDescC:
+    """ctypes descriptor from any object with n_in, n_freq, n_hidden, width, n_out."""
+    p = precision if precision is not None else getattr(desc, "precision", FP32)
+    if isinstance(p, str):
+        p = PRECISIONS[p]
+    return NetDescC(desc.n_in, desc.n_freq, desc.n_hidden, desc.width, desc.n_out, p)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise DDFError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    return t
+
+
+def param_count(desc, precision=None) -> int:
+    d = desc_c(desc, precision)
+    return int(lib().ddf_param_count(ctypes.byref(d)))
+
+
+def packed_bytes(desc, precision) -> int:
+    d = desc_c(desc, precision)
+    return int(lib().ddf_packed_bytes(ctypes.byref(d)))
+
+
+def pack(desc, precision, master: torch.Tensor, act_scales=None, out=None) -> torch.Tensor:
+    d = desc_c(desc, precision)
+    _dev(master, torch.float32, "master")
+    nbytes = int(lib().ddf_packed_bytes(ctypes.byref(d)))
+    if nbytes == 0:
+        _check(-1)
+    packed = out if out is not None else torch.empty(nbytes, dtype=torch.uint8, device=master.device)
+    sc = None
+    if act_scales is not None:
+        arr = np.ascontiguousarray(act_scales, dtype=np.float32)
+        sc = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    _check(lib().ddf_pack(ctypes.byref(d), _ptr(master), sc, _ptr(packed), _stream()))
+    return packed
+
+
+def query(desc, precision, packed: torch.Tensor, rays: torch.Tensor):
+    """(t, xi) for float32 SoA rays [6, n]."""
+    d = desc_c(desc, precision)
+    _dev(rays, torch.float32, "rays")
+    n = rays.shape[1]
+    t = torch.empty(n, dtype=torch.float32, device=rays.device)
+    xi = torch.empty(n, dtype=torch.float32, device=rays.device)
+    _check(lib().ddf_query(ctypes.byref(d), _ptr(packed), _ptr(rays), n, _ptr(t), _ptr(xi), _stream()))
+    return t, xi
+
+
+def query_into(desc_ct: NetDescC, packed, rays, t, xi, stream=None):
+    """Allocation-free query on prepared tensors (benchmark loop)."""
+    _check(lib().ddf_query(ctypes.byref(desc_ct), _ptr(packed), _ptr(rays), rays.shape[1], _ptr(t), _ptr(xi),
+                           stream if stream is not None else _stream()))
+
+
+def sdf_eval(desc, precision, packed, points):
+    d = desc_c(desc, precision)
+    _dev(points, torch.float32, "points")
+    n = points.shape[1]
+    s = torch.empty(n, dtype=torch.float32, device=points.device)
+    _check(lib().sdf_eval(ctypes.byref(d), _ptr(packed), _ptr(points), n, _ptr(s), _stream()))
+    return s
+
+
+def sphere_trace(desc, precision, packed, rays, max_steps=128, hit_eps=1e-4, t_max=6.0, ws=None):
+    """(t, hit, steps) of sphere tracing the SDF net along float32 SoA rays [6, n]."""
+    d = desc_c(desc, precision)
+    _dev(rays, torch.float32, "rays")
+    n = rays.shape[1]
+    dev = rays.device
+    t = torch.empty(n, dtype=torch.float32, device=dev)
+    hit = torch.empty(n, dtype=torch.uint8, device=dev)
+    steps = torch.empty(n, dtype=torch.int32, device=dev)
+    wsb = int(lib().sdf_trace_workspace_bytes(n))
+    if ws is None:
+        ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=dev)
+    _check(lib().sdf_sphere_trace(ctypes.byref(d), _ptr(packed), _ptr(rays), n, int(max_steps),
+                                  float(hit_eps), float(t_max), _ptr(t), _ptr(hit), _ptr(steps),
+                                  _ptr(ws), ws.numel(), _stream()))
+    return t, hit, steps
+
+
+def scene_prims(scene) -> np.ndarray:
+    """Device layout of an analytic scene: float32 [P, 16] = center, 1/axes, R^T row-major, pad."""
+    P = scene.n
+    out = np.zeros((P, 16), dtype=np.float32)
+    out[:, 0:3] = scene.centers
+    out[:, 3:6] = 1.0 / np.asarray(scene.axes)
+    out[:, 6:15] = np.transpose(np.asarray(scene.rot), (0, 2, 1)).reshape(P, 9)
+    return out
+
+
+def cast_targets(prims: torch.Tensor, rays: torch.Tensor):
+    """(t_gt, hit) by brute-force analytic ray casting on the GPU."""
+    _dev(prims, torch.float32, "prims")
+    _dev(rays, torch.float32, "rays")
+    n = rays.shape[1]
+    t = torch.empty(n, dtype=torch.float32, device=rays.device)
+    hit = torch.empty(n, dtype=torch.uint8, device=rays.device)
+    _check(lib().ddf_cast_targets(_ptr(prims), prims.shape[0], _ptr(rays), n, _ptr(t), _ptr(hit), _stream()))
+    return t, hit
+
+
+def train_workspace_bytes(desc, precision, batch) -> int:
+    d = desc_c(desc, precision)
+    return int(lib().ddf_train_workspace_bytes(ctypes.byref(d), int(batch)))
+
+
+def forward_train(desc, precision, packed, rays, ws):
+    d = desc_c(desc, precision)
+    n = rays.shape[1]
+    zt = torch.empty(n, dtype=torch.float32, device=rays.device)
+    zx = torch.empty(n, dtype=torch.float32, device=rays.device)
+    _check(lib().ddf_forward_train(ctypes.byref(d), _ptr(packed), _ptr(rays), n, _ptr(zt), _ptr(zx),
+                                   _ptr(ws), ws.numel(), _stream()))
+    return zt, zx
+
+
+def backward(desc, precision, packed, rays, grad_zt, grad_zx, ws):
+    d = desc_c(desc, precision)
+    n = rays.shape[1]
+    g = torch.empty(param_count(desc, precision), dtype=torch.float32, device=rays.device)
+    _check(lib().ddf_backward(ctypes.byref(d), _ptr(packed), _ptr(rays), n, _ptr(grad_zt), _ptr(grad_zx),
+                              _ptr(g), _ptr(ws), ws.numel(), _stream()))
+    return g
+
+
+def train_step(desc, precision, master, m, v, packed, rays, t_gt, hit, hp: TrainHParamsC, ws,
+               loss_out=None, flag=None, grad_out=None):
+    d = desc_c(desc, precision)
+    dev = rays.device
+    loss_out = loss_out if loss_out is not None else torch.empty(4, dtype=torch.float32, device=dev)
+    flag = flag if flag is not None else torch.empty(4, dtype=torch.int32, device=dev)
+    _check(lib().ddf_train_step(ctypes.byref(d), _ptr(master), _ptr(m), _ptr(v), _ptr(packed), _ptr(rays),
+                                _ptr(t_gt), _ptr(hit), rays.shape[1], ctypes.byref(hp), _ptr(loss_out),
+                                _ptr(flag), _ptr(grad_out), _ptr(ws), ws.numel(), _stream()))
+    return loss_out, flag
+
+
+def fp8_act_scales(desc, packed_fp32, rays) -> np.ndarray:
+    """Power-of-two FP8 input scales of hidden layers 2..n from a calibration batch."""
+    d = desc_c(desc, FP32)
+    n = rays.shape[1]
+    wsb = int(lib().ddf_fp8_calib_workspace_bytes(ctypes.byref(d), n))
+    ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=rays.device)
+    out = np.zeros(max(desc.n_hidden - 1, 1), dtype=np.float32)
+    _check(lib().ddf_fp8_act_scales(ctypes.byref(d), _ptr(packed_fp32), _ptr(rays), n,
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _ptr(ws), ws.numel(),
+                                    _stream()))
+    return out[:desc.n_hidden - 1]

@@ -1,0 +1,81 @@
+"""The C ABI library: it loads, exports every declared entry point, sizes buffers, and
+rejects bad arguments on the host before anything reaches the GPU (CPU-only tests)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2606_00817_amd import ddf
+from paper_2606_00817_amd import inputs as I
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ddf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:ddf|sdf)_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ddf.lib()
+    names = _declared()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(ddf.SIGNATURES), "binding and header disagree"
+
+
+def test_param_count_matches_master_layout():
+    for desc in (I.NET_TINY, I.NET_FULL, I.NET_LARGE, I.NET_SDF):
+        assert ddf.param_count(desc) == desc.param_count()
+    assert I.NET_FULL.param_count() == 11677698
+    assert ddf.packed_bytes(I.NET_FULL, "bf16") > 0
+
+
+def _err(rc):
+    return rc, ddf.lib().ddf_last_error().decode()
+
+
+def test_validation_errors_before_any_launch():
+    L = ddf.lib()
+    bad = ddf.desc_c(I.NetDesc(6, 4, 4, 100, 2))
+    assert L.ddf_param_count(ctypes.byref(bad)) == 0
+    d = ddf.desc_c(I.NET_TINY, "fp32")
+    fake = ctypes.c_void_p(0x10000)
+    mis = ctypes.c_void_p(0x10004)
+    rc, msg = _err(L.ddf_query(None, fake, fake, 10, fake, fake, None))
+    assert rc == -1 and "desc" in msg
+    rc, msg = _err(L.ddf_query(ctypes.byref(bad), fake, fake, 10, fake, fake, None))
+    assert rc == -2 and "width" in msg
+    rc, msg = _err(L.ddf_query(ctypes.byref(d), None, fake, 10, fake, fake, None))
+    assert rc == -1 and "packed" in msg
+    rc, msg = _err(L.ddf_query(ctypes.byref(d), fake, mis, 10, fake, fake, None))
+    assert rc == -1 and "aligned" in msg
+    rc, msg = _err(L.ddf_query(ctypes.byref(d), fake, fake, -3, fake, fake, None))
+    assert rc == -1
+    # n == 0 is a no-op that touches nothing
+    assert L.ddf_query(ctypes.byref(d), None, None, 0, None, None, None) == 0
+    sdf_d = ddf.desc_c(I.NET_SDF, "fp32")
+    rc, msg = _err(L.ddf_query(ctypes.byref(sdf_d), fake, fake, 10, fake, fake, None))
+    assert rc == -1 and "n_in 6" in msg
+    rc, msg = _err(L.sdf_sphere_trace(ctypes.byref(sdf_d), fake, fake, 100, 0, 1e-4, 6.0, fake, fake, None,
+                                      fake, 1 << 20, None))
+    assert rc == -1 and "max_steps" in msg
+    rc, msg = _err(L.sdf_sphere_trace(ctypes.byref(sdf_d), fake, fake, 100, 128, 1e-4, 6.0, fake, fake, None,
+                                      fake, 16, None))
+    assert rc == -3
+    fp8 = ddf.desc_c(I.NET_FULL, "fp8")
+    rc, msg = _err(L.ddf_pack(ctypes.byref(fp8), fake, None, fake, None))
+    assert rc == -1 and "act_scales" in msg
+    scales = (ctypes.c_float * 11)(*([0.5] * 10 + [0.3]))
+    rc, msg = _err(L.ddf_pack(ctypes.byref(fp8), fake, scales, fake, None))
+    assert rc == -1 and "power of two" in msg
+    rc, msg = _err(L.ddf_cast_targets(fake, 0, fake, 10, fake, fake, None))
+    assert rc == -1
+
+
+@pytest.mark.parametrize("code", [0, -1, -2, -3, -4])
+def test_status_strings(code):
+    assert ddf.lib().ddf_status_string(code)

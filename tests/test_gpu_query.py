@@ -1,0 +1,145 @@
+"""Parity of the HIP query path (C ABI) with the float64 oracle, element by element."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ddf_oracle as O
+from oracle import geometry as G
+from paper_2606_00817_amd import ddf
+from paper_2606_00817_amd import inputs as I
+from tests.helpers import cuda, fp32_forward_bound, fp32_forward_sigma, planted_box_sdf, box_sdf, U32
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def _check_fp32(desc, params, rays, t, xi, rigorous=False):
+    """Element-wise parity of a float32 query with the float64 oracle.
+
+    Tolerance: 8 sigma of the first-order float32 rounding-error model of the logits
+    (tests.helpers.fp32_forward_sigma) plus 8 ulp for the heads; with rigorous=True the
+    worst-case bound (any summation order) is checked as well."""
+    z, sig = fp32_forward_sigma(desc, params, rays)
+    t64 = O.softplus(z[:, 0]); xi64 = O.sigmoid(z[:, 1])
+    tol_t = 8 * sig[:, 0] + 8 * U32 * np.maximum(1.0, t64)
+    tol_x = 0.25 * 8 * sig[:, 1] + 8 * U32
+    dt = np.abs(t.astype(np.float64) - t64)
+    dx = np.abs(xi.astype(np.float64) - xi64)
+    assert np.all(np.isfinite(t)) and np.all(np.isfinite(xi))
+    bad = np.nonzero((dt > tol_t) | (dx > tol_x))[0]
+    assert bad.size == 0, (bad[:10], dt[bad[:10]], tol_t[bad[:10]])
+    if rigorous:
+        _, e = fp32_forward_bound(desc, params, rays)
+        assert np.all(dt <= e[:, 0] + 8 * U32 * np.maximum(1.0, t64))
+    return dt.max(), np.median(tol_t)
+
+
+@pytest.mark.parametrize("n", [4096, 1000, 33, 1])
+def test_fp32_query_tiny_net(n):
+    dev = cuda()
+    desc = I.NET_TINY
+    params = I.test_params(desc, 1)
+    rays = I.free_rays(I.scene_spheres(16, 1), n, 11)
+    packed = ddf.pack(desc, "fp32", _t(params, dev))
+    t, xi = ddf.query(desc, "fp32", packed, _t(rays, dev))
+    torch.cuda.synchronize()
+    dmax, tol = _check_fp32(desc, params, rays, t.cpu().numpy(), xi.cpu().numpy(), rigorous=True)
+    print(f"tiny fp32 n={n}: max|dt|={dmax:.3g} (median tolerance {tol:.3g})")
+
+
+@pytest.mark.parametrize("width", [1024, 512, 256])
+def test_fp32_query_wide_net_ragged(width):
+    dev = cuda()
+    desc = I.NetDesc(6, 10, 12, width, 2)
+    params = I.test_params(desc, 2)
+    sc = I.scene_mixed(256, 2)
+    rays = I.shadow_rays(sc, 32 * 37 + 13, 12)       # 38 tiles of 32, ragged tail
+    packed = ddf.pack(desc, "fp32", _t(params, dev))
+    t, xi = ddf.query(desc, "fp32", packed, _t(rays, dev))
+    torch.cuda.synchronize()
+    dmax, tol = _check_fp32(desc, params, rays, t.cpu().numpy(), xi.cpu().numpy())
+    print(f"width {width} fp32: max|dt|={dmax:.3g} (median tolerance {tol:.3g})")
+
+
+def test_bf16_query_matches_emulated_oracle():
+    dev = cuda()
+    desc = I.NET_FULL
+    params = I.test_params(desc, 3)
+    sc = I.scene_mixed(256, 2)
+    rays = I.shadow_rays(sc, 64 * 23 + 5, 13)
+    packed = ddf.pack(desc, "bf16", _t(params, dev))
+    t, xi = ddf.query(desc, "bf16", packed, _t(rays, dev))
+    torch.cuda.synchronize()
+    t = t.cpu().numpy().astype(np.float64); xi = xi.cpu().numpy().astype(np.float64)
+    te, xe, zt, zx = O.ddf_query_emulated(desc, params, rays, "bf16")
+    t64, x64, _, _ = O.ddf_query(desc, params, rays)
+    d_em = np.abs(t - te)
+    d_64 = np.abs(t - t64)
+    print(f"bf16 vs emulated: max {d_em.max():.3g} mean {d_em.mean():.3g}; vs fp64: max {d_64.max():.3g} "
+          f"mean {d_64.mean():.3g}")
+    assert np.all(np.isfinite(t))
+    assert d_em.mean() <= 1e-3 * max(1.0, np.abs(te).mean())
+    assert d_em.max() <= 2e-2 * max(1.0, np.abs(te).max())
+    assert np.abs(xi - xe).max() <= 1e-2
+
+
+def test_sdf_eval_planted_box():
+    dev = cuda()
+    desc = I.NetDesc(3, 10, 12, 1024, 1)
+    half = [0.3, 0.5, 0.7]
+    params = planted_box_sdf(desc, half, 5)
+    pts = I.sdf_points(64 * 5 + 7, 4)
+    packed = ddf.pack(desc, "fp32", _t(params, dev))
+    s = ddf.sdf_eval(desc, "fp32", packed, _t(pts, dev)).cpu().numpy()
+    ref = O.sdf_eval(desc, params, pts.T.astype(np.float64))
+    exact = box_sdf(pts.T.astype(np.float64), half)
+    np.testing.assert_allclose(ref, exact, atol=1e-6)
+    np.testing.assert_allclose(s, ref, atol=2e-5)
+
+
+def test_cast_targets_match_oracle():
+    dev = cuda()
+    sc = I.scene_ellipsoids(1024, 3)
+    rays = I.train_rays(sc, 4096 + 77, 1000)
+    prims = _t(ddf.scene_prims(sc), dev)
+    t, hit = ddf.cast_targets(prims, _t(rays, dev))
+    torch.cuda.synchronize()
+    t = t.cpu().numpy(); hit = hit.cpu().numpy().astype(bool)
+    tg, hg, _ = G.intersect_soa(sc, rays)
+    agree = hit == hg
+    # a flip is only allowed at a grazing ray (float32 discriminant near zero)
+    assert agree.mean() > 0.998
+    both = hit & hg
+    np.testing.assert_allclose(t[both], tg[both], rtol=2e-4, atol=2e-5)
+    assert np.all(np.isinf(t[~hit]))
+
+
+def test_sphere_trace_planted_box_matches_oracle():
+    dev = cuda()
+    desc = I.NetDesc(3, 10, 6, 256, 1)
+    half = [0.3, 0.5, 0.7]
+    params = planted_box_sdf(desc, half, 7)
+    rng = np.random.default_rng(3)
+    n = 64 * 9 + 3
+    o = rng.uniform(-1.5, 1.5, (n, 3))
+    o = o[np.max(np.abs(o) - half, axis=1) > 0.05][: 64 * 5 + 3]
+    aim = rng.uniform(-0.2, 0.2, (len(o), 3))
+    d = np.where(rng.uniform(size=(len(o), 1)) < 0.7, aim - o, rng.standard_normal((len(o), 3)))
+    rays = I._soa(o, d)
+    packed = ddf.pack(desc, "fp32", _t(params, dev))
+    t, hit, steps = ddf.sphere_trace(desc, "fp32", packed, _t(rays, dev), max_steps=128, hit_eps=1e-4, t_max=6.0)
+    torch.cuda.synchronize()
+    t = t.cpu().numpy(); hit = hit.cpu().numpy().astype(bool); steps = steps.cpu().numpy()
+    ro = rays[0:3].T.astype(np.float64); rd = rays[3:6].T.astype(np.float64)
+    tr, hr, sr, done = G.sphere_trace(lambda p: O.sdf_eval(desc, params, p), ro, rd, 128, 1e-4, 6.0)
+    same = (hit == hr) & (steps == sr)
+    print(f"trace: {hit.mean():.2f} hit, steps mean {steps.mean():.1f}, agree {same.mean():.4f}")
+    assert hit.mean() > 0.3 and (~hit).mean() > 0.05
+    assert same.mean() > 0.98
+    np.testing.assert_allclose(t[same & hit], tr[same & hit], atol=1e-4)
+    # a hit point is on the box surface (the planted SDF is exact there)
+    p = ro[hit] + t[hit, None] * rd[hit]
+    assert np.all(np.abs(box_sdf(p, half)) < 2e-4)
