@@ -45,6 +45,8 @@ int check_desc(const ddf_net_desc* d) {
     return fail(DDF_ERR_UNSUPPORTED, "padded layer-1 input (%d) wider than the hidden width (%d)", L.k1, d->width);
   if (d->precision == DDF_FP8_E4M3 && d->n_hidden < 2)
     return fail(DDF_ERR_UNSUPPORTED, "fp8 needs at least two hidden layers");
+  if (d->precision == DDF_FP8_E4M3 && (d->width < 256 || L.k1 > 256))
+    return fail(DDF_ERR_UNSUPPORTED, "fp8 needs width >= 256 and at most 128 padded input features");
   return DDF_OK;
 }
 
@@ -74,6 +76,19 @@ __global__ void trace_init_kernel(int64_t n, int32_t* idx0, int32_t* counts, int
     hit[i] = 0;
     if (steps) steps[i] = 0;
   }
+}
+
+__global__ void zero_u32_kernel(unsigned int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// Smallest power of two s with amax / s <= 448 (1 for amax <= 0).
+static float pow2_scale_e4m3(float amax) {
+  if (!(amax > 0.f)) return 1.f;
+  int e;
+  const float m = frexpf(amax, &e);   // amax = m 2^e, 0.5 <= m < 1
+  return ldexpf(1.f, e - 9 + (2.f * m > 1.75f ? 1 : 0));
 }
 
 // ------------------------------------------------------------------ supervision targets
@@ -206,6 +221,48 @@ int sdf_eval(const ddf_net_desc* d, const void* packed, const float* points, int
   a.in = points; a.n = n; a.stride = n; a.mode = kModeSdf; a.out0 = sdf;
   g_err[0] = 0;
   return hip_status(launch_forward(*d, a, n, (hipStream_t)stream), "sdf_eval launch");
+}
+
+size_t ddf_fp8_calib_workspace_bytes(const ddf_net_desc* d, int64_t n) {
+  if (check_desc(d) != DDF_OK || n < 0) return 0;
+  return 256 + (size_t)align256(4 * n) * 2;
+}
+
+int ddf_fp8_act_scales(const ddf_net_desc* d, const void* packed_fp32, const float* rays, int64_t n,
+                       float* act_scales_host, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_desc(d))) return rc;
+  if (d->n_in != 6 || d->n_out != 2) return fail(DDF_ERR_INVALID_ARG, "calibration needs a DDF net (n_in 6, n_out 2)");
+  if (n < 1 || n > (int64_t)INT32_MAX) return fail(DDF_ERR_INVALID_ARG, "calibration needs 1..2^31-1 rays");
+  if (!act_scales_host) return fail(DDF_ERR_INVALID_ARG, "act_scales_host is NULL");
+  if ((rc = check_ptr(packed_fp32, "packed_fp32")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(ws, "ws")))
+    return rc;
+  if (ws_bytes < ddf_fp8_calib_workspace_bytes(d, n))
+    return fail(DDF_ERR_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, ddf_fp8_calib_workspace_bytes(d, n));
+  ddf_net_desc d32 = *d;
+  d32.precision = DDF_FP32;
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* w = static_cast<uint8_t*>(ws);
+  unsigned int* amax = reinterpret_cast<unsigned int*>(w);
+  zero_u32_kernel<<<1, 64, 0, st>>>(amax, kMaxLayers);
+  if ((rc = hip_status(hipGetLastError(), "calibration init"))) return rc;
+  FwdArgs a = base_args(d32, packed_fp32);
+  a.in = rays; a.n = n; a.stride = n; a.mode = kModeCalib;
+  a.out0 = reinterpret_cast<float*>(w + 256);
+  a.out1 = reinterpret_cast<float*>(w + 256 + align256(4 * n));
+  a.amax = amax;
+  g_err[0] = 0;
+  if ((rc = hip_status(launch_forward(d32, a, n, st), "calibration launch"))) return rc;
+  unsigned int host[kMaxLayers];
+  if ((rc = hip_status(hipMemcpyAsync(host, amax, sizeof(host), hipMemcpyDeviceToHost, st), "calibration copy")))
+    return rc;
+  if ((rc = hip_status(hipStreamSynchronize(st), "calibration sync"))) return rc;
+  for (int l = 0; l + 1 < d->n_hidden; ++l) {
+    float m;
+    memcpy(&m, &host[l], 4);
+    act_scales_host[l] = pow2_scale_e4m3(m);
+  }
+  return DDF_OK;
 }
 
 size_t sdf_trace_workspace_bytes(int64_t n) {

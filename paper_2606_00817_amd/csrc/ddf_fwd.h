@@ -8,7 +8,8 @@ enum FwdMode {
   kModeQuery = 0,   // t = softplus(z_t), xi = sigmoid(z_xi)
   kModeTrain = 1,   // raw logits + activations kept for the backward pass
   kModeSdf = 2,     // signed distance z_0 at points
-  kModeTrace = 3    // one sphere-tracing step over the active-ray list
+  kModeTrace = 3,   // one sphere-tracing step over the active-ray list
+  kModeCalib = 4    // query that records max h_l of hidden layers 1..n-1 (FP8 scales)
 };
 
 struct FwdArgs {
@@ -35,6 +36,8 @@ struct FwdArgs {
   int32_t* steps;         // may be null
   int step;               // 0-based step index
   float hit_eps, t_max;
+  // calib mode: per hidden layer, the max post-ReLU value as ordered uint bits
+  unsigned int* amax;
 };
 
 __device__ inline void trace_update(const FwdArgs& a, int32_t src, float s) {
@@ -51,8 +54,77 @@ __device__ inline void trace_update(const FwdArgs& a, int32_t src, float s) {
   }
 }
 
+// Row of the 32x32 accumulator held in register v by `lane`.
+__device__ inline int acc_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+// Encoded inputs of rays [ray0, ray0 + M) into X[:, 0:k1]; padding columns are zero.
+// Reduced precisions store the bf16 hi part in columns [0, k1_half) and the lo part
+// in [k1_half, k1).  Train mode also writes the features (fp32, or bf16 hi) to slab 0
+// of the activation store, layout [rows / 8][k1_half][8].
+template <class E, int M, int LDX, int MODE>
+__device__ void encode_tile(const FwdArgs& a, int64_t ray0, E* X) {
+  const int n_in = a.n_in, nf = a.n_freq;
+  const int khalf = a.lay.k1_half;
+  const bool split = sizeof(E) == 2;
+  const int items = M * n_in * (1 + nf);
+  for (int idx = threadIdx.x; idx < items; idx += kThreads) {
+    const int r = idx % M;
+    const int rest = idx / M;
+    const int j = rest % n_in;
+    const int kk = rest / n_in;
+    const int64_t g = ray0 + r;
+    float v = 0.f;
+    if (g < a.n) {
+      if (MODE == kModeTrace) {
+        const int32_t src = a.idx[g];
+        const float tt = a.t_state[src];
+        v = fmaf(tt, a.in[(int64_t)(3 + j) * a.stride + src], a.in[(int64_t)j * a.stride + src]);
+      } else {
+        v = a.in[(int64_t)j * a.stride + g];
+      }
+    }
+    float f0, f1 = 0.f;
+    int c0, c1 = -1;
+    if (kk == 0) {
+      f0 = v; c0 = j;
+    } else {
+      sincospif(ldexpf(v, kk - 1), &f0, &f1);
+      c0 = (2 * kk - 1) * n_in + j;
+      c1 = c0 + n_in;
+    }
+    for (int w = 0; w < 2; ++w) {
+      const int c = w == 0 ? c0 : c1;
+      if (c < 0) break;
+      const float f = w == 0 ? f0 : f1;
+      if (split) {
+        const E hi = (E)f;
+        const E lo = (E)(f - (float)hi);
+        X[r * LDX + c] = hi;
+        X[r * LDX + khalf + c] = lo;
+      } else {
+        X[r * LDX + c] = (E)f;
+      }
+      if (MODE == kModeTrain)
+        reinterpret_cast<E*>(a.act)[((g >> 3) * khalf + c) * 8 + (g & 7)] = (E)f;
+    }
+  }
+  const int pad = khalf - a.lay.n_feat;
+  for (int idx = threadIdx.x; idx < M * pad; idx += kThreads) {
+    const int r = idx % M, c = a.lay.n_feat + idx / M;
+    X[r * LDX + c] = (E)0.f;
+    if (split) X[r * LDX + khalf + c] = (E)0.f;
+    if (MODE == kModeTrain) {
+      const int64_t g = ray0 + r;
+      reinterpret_cast<E*>(a.act)[((g >> 3) * khalf + c) * 8 + (g & 7)] = (E)0.f;
+    }
+  }
+}
+
+
 hipError_t launch_forward(const ddf_net_desc& d, const FwdArgs& a, int64_t n_items,
                           hipStream_t st);
+hipError_t launch_forward8(const ddf_net_desc& d, const FwdArgs& a, int64_t n_items,
+                           hipStream_t st);
 
 hipError_t launch_pack(const ddf_net_desc& d, const float* master, const float* act_scales,
                        void* packed, hipStream_t st, bool with_transposed);

@@ -64,25 +64,49 @@ struct Chain {
 
   // acc[rt][t] += X[rt rows][0:K] * W[(nt0 + t) neuron tile][0:K]^T.  The weight blocks of
   // one layer are read through a buffer resource: per-lane offset lane * 16 bytes, the
-  // block offset ((nt0 + t) KB + k) * 1 KiB is wave-uniform.  KB is even; the loads run
-  // one block ahead, and the one past the end of the layer is bounds-checked by the
-  // buffer resource (it returns zeros and is never used).
-  static __device__ inline void gemm(f32x16 (&acc)[RT][NT], const E* X, const void* W, int KB,
+  // block offset ((nt0 + t) KB + k) * 1 KiB is wave-uniform.  Loads run three blocks
+  // ahead in a ring of four; KB is a multiple of 4, and the loads past the end of the
+  // layer are bounds-checked by the buffer resource (they return zeros, never used).
+  template <int KBC>
+  static __device__ inline void gemm(f32x16 (&acc)[RT][NT], const E* X, const void* W, int KB_rt,
                                      int nt0, int lane) {
+    const int KB = KBC > 0 ? KBC : KB_rt;   // compile-time for the hidden layers: fully unrolled
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, WIDTH * KB * 32, 0x00020000);
     const int voff = lane * 16;
+    const int base = nt0 * KB * 1024;
+    const int tstride = KB * 1024;
     const E* xrow = X + (lane & 31) * LDX + (P::KBLK / 2) * (lane >> 5);
-    BFrag b0[NT], b1[NT];
+    BFrag b0[NT], b1[NT], b2[NT], b3[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) b0[t] = load_b(rs, voff, ((nt0 + t) * KB) * 1024);
-    for (int k = 0; k < KB; k += 2) {
+    for (int t = 0; t < NT; ++t) {
+      b0[t] = load_b(rs, voff, base + t * tstride);
+      b1[t] = load_b(rs, voff, base + t * tstride + 1024);
+      b2[t] = load_b(rs, voff, base + t * tstride + 2048);
+    }
+#pragma unroll (KBC > 0 ? KBC / 4 : 1)
+    for (int k = 0; k < KB; k += 4) {
+      const int kb = base + k * 1024;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b1[t] = load_b(rs, voff, ((nt0 + t) * KB + k + 1) * 1024);
+      for (int t = 0; t < NT; ++t) b3[t] = load_b(rs, voff, kb + t * tstride + 3 * 1024);
+      __builtin_amdgcn_sched_barrier(0);
       step(acc, xrow, k, b0);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b0[t] = load_b(rs, voff, ((nt0 + t) * KB + k + 2) * 1024);
+      for (int t = 0; t < NT; ++t) b0[t] = load_b(rs, voff, kb + t * tstride + 4 * 1024);
+      __builtin_amdgcn_sched_barrier(0);
       step(acc, xrow, k + 1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b1[t] = load_b(rs, voff, kb + t * tstride + 5 * 1024);
+      __builtin_amdgcn_sched_barrier(0);
+      step(acc, xrow, k + 2, b2);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b2[t] = load_b(rs, voff, kb + t * tstride + 6 * 1024);
+      __builtin_amdgcn_sched_barrier(0);
+      step(acc, xrow, k + 3, b3);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 
@@ -97,72 +121,6 @@ struct Chain {
       for (int t = 0; t < NT; ++t) P::mma(acc[rt][t], av[rt], b[t]);
   }
 };
-
-// Row of the 32x32 accumulator held in register v by `lane`.
-__device__ inline int acc_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
-
-// Encoded inputs of rays [ray0, ray0 + M) into X[:, 0:k1]; padding columns are zero.
-// Reduced precisions store the bf16 hi part in columns [0, k1_half) and the lo part
-// in [k1_half, k1).  Train mode also writes the features (fp32, or bf16 hi) to slab 0
-// of the activation store, layout [rows / 8][k1_half][8].
-template <class E, int M, int LDX, int MODE>
-__device__ void encode_tile(const FwdArgs& a, int64_t ray0, E* X) {
-  const int n_in = a.n_in, nf = a.n_freq;
-  const int khalf = a.lay.k1_half;
-  const bool split = sizeof(E) == 2;
-  const int items = M * n_in * (1 + nf);
-  for (int idx = threadIdx.x; idx < items; idx += kThreads) {
-    const int r = idx % M;
-    const int rest = idx / M;
-    const int j = rest % n_in;
-    const int kk = rest / n_in;
-    const int64_t g = ray0 + r;
-    float v = 0.f;
-    if (g < a.n) {
-      if (MODE == kModeTrace) {
-        const int32_t src = a.idx[g];
-        const float tt = a.t_state[src];
-        v = fmaf(tt, a.in[(int64_t)(3 + j) * a.stride + src], a.in[(int64_t)j * a.stride + src]);
-      } else {
-        v = a.in[(int64_t)j * a.stride + g];
-      }
-    }
-    float f0, f1 = 0.f;
-    int c0, c1 = -1;
-    if (kk == 0) {
-      f0 = v; c0 = j;
-    } else {
-      sincospif(ldexpf(v, kk - 1), &f0, &f1);
-      c0 = (2 * kk - 1) * n_in + j;
-      c1 = c0 + n_in;
-    }
-    for (int w = 0; w < 2; ++w) {
-      const int c = w == 0 ? c0 : c1;
-      if (c < 0) break;
-      const float f = w == 0 ? f0 : f1;
-      if (split) {
-        const E hi = (E)f;
-        const E lo = (E)(f - (float)hi);
-        X[r * LDX + c] = hi;
-        X[r * LDX + khalf + c] = lo;
-      } else {
-        X[r * LDX + c] = (E)f;
-      }
-      if (MODE == kModeTrain)
-        reinterpret_cast<E*>(a.act)[((g >> 3) * khalf + c) * 8 + (g & 7)] = (E)f;
-    }
-  }
-  const int pad = khalf - a.lay.n_feat;
-  for (int idx = threadIdx.x; idx < M * pad; idx += kThreads) {
-    const int r = idx % M, c = a.lay.n_feat + idx / M;
-    X[r * LDX + c] = (E)0.f;
-    if (split) X[r * LDX + khalf + c] = (E)0.f;
-    if (MODE == kModeTrain) {
-      const int64_t g = ray0 + r;
-      reinterpret_cast<E*>(a.act)[((g >> 3) * khalf + c) * 8 + (g & 7)] = (E)0.f;
-    }
-  }
-}
 
 template <class P, int WIDTH, int MODE>
 __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
@@ -196,7 +154,10 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
-    C::gemm(acc, X, W, K / P::KBLK, nt0, lane);
+    if (l == 0)
+      C::template gemm<0>(acc, X, W, K / P::KBLK, nt0, lane);
+    else
+      C::template gemm<WIDTH / P::KBLK>(acc, X, W, K / P::KBLK, nt0, lane);
     __syncthreads();   // every wave is done reading X
 
     const float* bias = bias_all + (int64_t)l * WIDTH;
@@ -227,6 +188,14 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
         } else {
 #pragma unroll
           for (int v = 0; v < 16; ++v) X[(rt * 32 + acc_row(v, lane)) * LDX + n] = (E)acc[rt][t][v];
+          if (MODE == kModeCalib) {
+            float m = 0.f;
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+              if (ray0 + rt * 32 + acc_row(v, lane) < n_act) m = fmaxf(m, acc[rt][t][v]);
+            for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+            if (lane == 0) atomicMax(a.amax + l, __float_as_uint(m));
+          }
         }
         if (slab) {
 #pragma unroll
@@ -267,6 +236,7 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
     for (int w = 0; w < kWaves; ++w) { z0 += headp[w][r][0]; z1 += headp[w][r][1]; }
     switch (MODE) {
       case kModeQuery:
+      case kModeCalib:
         a.out0[g] = softplusf_(z0);
         a.out1[g] = sigmoidf_(z1);
         break;
@@ -292,6 +262,7 @@ static hipError_t launch_t(const FwdArgs& a, int64_t n_tiles, hipStream_t st) {
     case kModeQuery: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeQuery>), grid, block, 0, st, a); break;
     case kModeTrain: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrain>), grid, block, 0, st, a); break;
     case kModeSdf: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeSdf>), grid, block, 0, st, a); break;
+    case kModeCalib: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeCalib>), grid, block, 0, st, a); break;
     default: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrace>), grid, block, 0, st, a); break;
   }
   return hipGetLastError();
@@ -308,6 +279,8 @@ hipError_t launch_forward(const ddf_net_desc& d, const FwdArgs& a, int64_t n_ite
       case 512: return launch_t<PF32, 512>(a, tiles, st);
       case 1024: return launch_t<PF32, 1024>(a, tiles, st);
     }
+  } else if (d.precision == DDF_FP8_E4M3) {
+    return launch_forward8(d, a, n_items, st);
   } else if (d.precision == DDF_BF16) {
     switch (d.width) {
       case 128: return launch_t<PBF16, 128>(a, tiles, st);

@@ -1,0 +1,263 @@
+// FP8 (OCP e4m3) forward pass of the DDF / SDF MLP on the gfx950 matrix cores.
+//
+// Same structure as the fp32/bf16 chain (one workgroup of 4 waves owns a ray
+// tile for the whole network, activations resident in LDS, weight blocks
+// streamed from global memory), with M = 128 rays per workgroup:
+//  * layer 1 reads the encoded input split as bf16 hi + lo
+//    (v_mfma_f32_32x32x16_bf16) with bf16 weights;
+//  * hidden layers 2..n read e4m3 activations and e4m3 weights
+//    (v_mfma_scale_f32_32x32x64_f8f6f4 with unit block scales), accumulate in
+//    fp32 and rescale the sum by the layer's power-of-two s_A s_W;
+//  * the epilogue adds the bias, applies ReLU and stores e4m3(h / s_A,next)
+//    into LDS; the heads read the fp32 output of the last layer.
+// A wave owns width/4 output neurons; with 128 rays the accumulators of all of
+// them do not fit at once, so each layer runs in two passes over half of the
+// wave's neurons, the first pass's e4m3 results waiting in registers until the
+// layer's input may be overwritten.
+#include "ddf_fwd.h"
+#include "ddf_internal.h"
+
+namespace ddf {
+
+namespace {
+
+constexpr int kM8 = 128;                 // rays per workgroup
+constexpr int kRT8 = kM8 / 32;           // 32-ray tiles
+constexpr int kLDG = 256 + 8;            // bf16 row stride of the layer-1 input (k1 <= 256)
+
+__device__ inline i32x8 lds_a8(const uint8_t* p) {
+  const i32x4 lo = *reinterpret_cast<const i32x4*>(p);
+  const i32x4 hi = *reinterpret_cast<const i32x4*>(p + 16);
+  return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+__device__ inline i32x8 buf_b8(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+  const i32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+  const i32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16, soff, 0);
+  return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+__device__ inline uint8_t to_e4m3(float x) {
+  x = fminf(fmaxf(x, -448.f), 448.f);        // saturate, then round to nearest even
+  return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, x, 0, false) & 0xff);
+}
+
+// acc[rt][t] += G[rt rows][0:K1] * W1[tile (tile0 + t)][0:K1]^T   (bf16 operands)
+template <int NTP>
+__device__ inline void gemm_l1(f32x16 (&acc)[kRT8][NTP], const __bf16* G, const void* W, int KB,
+                               int tile0, int lane, int width) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, width * KB * 32, 0x00020000);
+  const int voff = lane * 16;
+  const __bf16* xrow = G + (lane & 31) * kLDG + 8 * (lane >> 5);
+  for (int k = 0; k < KB; ++k) {
+    bf16x8 b[NTP];
+#pragma unroll
+    for (int t = 0; t < NTP; ++t)
+      b[t] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, ((tile0 + t) * KB + k) * 1024, 0));
+    bf16x8 av[kRT8];
+#pragma unroll
+    for (int rt = 0; rt < kRT8; ++rt) av[rt] = *reinterpret_cast<const bf16x8*>(xrow + rt * 32 * kLDG + k * 16);
+#pragma unroll
+    for (int rt = 0; rt < kRT8; ++rt)
+#pragma unroll
+      for (int t = 0; t < NTP; ++t)
+        acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt], b[t], acc[rt][t], 0, 0, 0);
+  }
+}
+
+// acc[rt][t] += X[rt rows][0:K] * W[tile (tile0 + t)][0:K]^T   (e4m3 operands, 2 KiB blocks).
+// K = KB * 64 is a compile-time constant: the k loop is fully unrolled, with the weight
+// loads running two blocks ahead in a ring of three (loads past the end of the layer are
+// bounds-checked by the buffer resource: they return zeros and are never used).
+template <int NTP, int LDX, int KB>
+__device__ inline void gemm_f8(f32x16 (&acc)[kRT8][NTP], const uint8_t* X, const void* W, int tile0,
+                               int lane, int width) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, width * KB * 64, 0x00020000);
+  const int voff = lane * 32;
+  const int base = tile0 * KB * 2048;
+  const uint8_t* xrow = X + (lane & 31) * LDX + 32 * (lane >> 5);
+  i32x8 b[3][NTP];
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int t = 0; t < NTP; ++t) b[s][t] = buf_b8(rs, voff, base + (t * KB + s) * 2048);
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+#pragma unroll
+    for (int t = 0; t < NTP; ++t) b[(k + 2) % 3][t] = buf_b8(rs, voff, base + (t * KB + k + 2) * 2048);
+    __builtin_amdgcn_sched_barrier(0);
+    i32x8 av[kRT8];
+#pragma unroll
+    for (int rt = 0; rt < kRT8; ++rt) av[rt] = lds_a8(xrow + rt * 32 * LDX + k * 64);
+#pragma unroll
+    for (int rt = 0; rt < kRT8; ++rt)
+#pragma unroll
+      for (int t = 0; t < NTP; ++t)
+        acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[rt], b[k % 3][t], acc[rt][t], 0, 0, 0,
+                                                                     127, 0, 127);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+}  // namespace
+
+template <int WIDTH, int MODE>
+__global__ __launch_bounds__(kThreads, 1) void fwd8_kernel(FwdArgs a) {
+  constexpr int NTW = WIDTH / 32 / kWaves;   // 32-neuron tiles per wave
+  constexpr int NTP = NTW / 2;               // tiles per pass
+  constexpr int LDX = WIDTH + 16;            // e4m3 row stride (bytes)
+  constexpr int XBYTES = kM8 * LDX > kM8 * kLDG * 2 ? kM8 * LDX : kM8 * kLDG * 2;
+  __shared__ __attribute__((aligned(16))) uint8_t smem[XBYTES];
+  __shared__ float headp[kWaves][kM8][2];
+  uint8_t* X = smem;
+  __bf16* G = reinterpret_cast<__bf16*>(smem);
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t ray0 = (int64_t)blockIdx.x * kM8;
+  if (MODE == kModeTrace && ray0 >= *a.count) return;
+  const int64_t n_act = MODE == kModeTrace ? (int64_t)*a.count : a.n;
+  FwdArgs aa = a;
+  aa.n = n_act;
+
+  encode_tile<__bf16, kM8, kLDG, MODE>(aa, ray0, G);
+  for (int i = threadIdx.x; i < kWaves * kM8 * 2; i += kThreads) (&headp[0][0][0])[i] = 0.f;
+  __syncthreads();
+
+  const float* bias_all = reinterpret_cast<const float*>(a.packed + a.lay.b_off);
+  const float* hw = reinterpret_cast<const float*>(a.packed + a.lay.head_w_off);
+  const float* hb = reinterpret_cast<const float*>(a.packed + a.lay.head_b_off);
+  const float* scales = reinterpret_cast<const float*>(a.packed + a.lay.scale_off);
+
+  for (int l = 0; l < a.n_hidden; ++l) {
+    const bool last = (l + 1 == a.n_hidden);
+    const float dq = scales[4 * l + kDequant];
+    const float qn = scales[4 * l + kQuantNext];
+    const float* bias = bias_all + (int64_t)l * WIDTH;
+    const void* W = a.packed + a.lay.w_off[l];
+    uint32_t hold[kRT8][NTP][4];             // pass-0 e4m3 results, 4 rows per word
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int tile0 = wave * NTW + p * NTP;
+      f32x16 acc[kRT8][NTP];
+#pragma unroll
+      for (int rt = 0; rt < kRT8; ++rt)
+#pragma unroll
+        for (int t = 0; t < NTP; ++t) acc[rt][t] = f32x16{};
+      if (l == 0)
+        gemm_l1<NTP>(acc, G, W, a.lay.k1 / 16, tile0, lane, WIDTH);
+      else
+        gemm_f8<NTP, LDX, WIDTH / 64>(acc, X, W, tile0, lane, WIDTH);
+      if (p == 1) {
+        __syncthreads();   // every wave is done reading this layer's input
+        if (!last) {
+          // the pass-0 results go in first, then pass 1 straight from the accumulators
+#pragma unroll
+          for (int rt = 0; rt < kRT8; ++rt)
+#pragma unroll
+            for (int t = 0; t < NTP; ++t) {
+              const int n = (wave * NTW + t) * 32 + (lane & 31);
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                  X[(rt * 32 + acc_row(4 * q + i, lane)) * LDX + n] = (uint8_t)(hold[rt][t][q] >> (8 * i));
+            }
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < kRT8; ++rt) {
+        float hp0[16], hp1[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) { hp0[v] = 0.f; hp1[v] = 0.f; }
+#pragma unroll
+        for (int t = 0; t < NTP; ++t) {
+          const int n = (tile0 + t) * 32 + (lane & 31);
+          const float bv = bias[n];
+          float y[16];
+#pragma unroll
+          for (int v = 0; v < 16; ++v) y[v] = fmaxf(fmaf(acc[rt][t][v], dq, bv), 0.f);
+          if (last) {
+            const float w0 = hw[n];
+            const float w1 = a.n_out > 1 ? hw[WIDTH + n] : 0.f;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              hp0[v] = fmaf(w0, y[v], hp0[v]);
+              hp1[v] = fmaf(w1, y[v], hp1[v]);
+            }
+          } else if (p == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              uint32_t w = 0;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) w |= (uint32_t)to_e4m3(y[4 * q + i] * qn) << (8 * i);
+              hold[rt][t][q] = w;
+            }
+          } else {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) X[(rt * 32 + acc_row(v, lane)) * LDX + n] = to_e4m3(y[v] * qn);
+          }
+        }
+        if (last) {
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            hp0[v] = wave_sum32(hp0[v]);
+            hp1[v] = wave_sum32(hp1[v]);
+          }
+          if ((lane & 31) == 0) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int r = rt * 32 + acc_row(v, lane);
+              headp[wave][r][0] += hp0[v];   // pass 0 then pass 1, same lane: fixed order
+              headp[wave][r][1] += hp1[v];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  for (int r = threadIdx.x; r < kM8; r += kThreads) {
+    const int64_t g = ray0 + r;
+    if (g >= n_act) continue;
+    float z0 = hb[0], z1 = a.n_out > 1 ? hb[1] : 0.f;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) { z0 += headp[w][r][0]; z1 += headp[w][r][1]; }
+    if (MODE == kModeQuery) {
+      a.out0[g] = softplusf_(z0);
+      a.out1[g] = sigmoidf_(z1);
+    } else if (MODE == kModeSdf) {
+      a.out0[g] = z0;
+    } else if (MODE == kModeTrace) {
+      trace_update(a, a.idx[g], z0);
+    }
+  }
+}
+
+template <int WIDTH>
+static hipError_t launch8_t(const FwdArgs& a, int64_t n_tiles, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  const dim3 grid((unsigned)n_tiles), block(kThreads);
+  switch (a.mode) {
+    case kModeQuery: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeQuery>), grid, block, 0, st, a); break;
+    case kModeSdf: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeSdf>), grid, block, 0, st, a); break;
+    case kModeTrace: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeTrace>), grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_forward8(const ddf_net_desc& d, const FwdArgs& a, int64_t n_items, hipStream_t st) {
+  const int64_t tiles = (n_items + kM8 - 1) / kM8;
+  switch (d.width) {
+    case 256: return launch8_t<256>(a, tiles, st);
+    case 512: return launch8_t<512>(a, tiles, st);
+    case 1024: return launch8_t<1024>(a, tiles, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace ddf

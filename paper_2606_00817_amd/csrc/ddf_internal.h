@@ -73,7 +73,7 @@ inline Layout make_layout(const ddf_net_desc& d) {
   Layout L{};
   Geo g = geo_of(d.precision);
   L.n_feat = d.n_in * (1 + 2 * d.n_freq);
-  L.k1_half = round_up(L.n_feat, 2 * g.kblk1);   // an even number of k blocks
+  L.k1_half = round_up(L.n_feat, 4 * g.kblk1);   // a multiple of 4 k blocks
   L.k1 = d.precision == DDF_FP32 ? L.k1_half : 2 * L.k1_half;
   int64_t off = 0;
   for (int l = 0; l < d.n_hidden; ++l) {

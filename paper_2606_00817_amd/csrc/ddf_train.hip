@@ -26,11 +26,4 @@ int ddf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
   return fail(DDF_ERR_UNSUPPORTED, "training not built yet");
 }
 
-size_t ddf_fp8_calib_workspace_bytes(const ddf_net_desc* d, int64_t n) { return 0; }
-
-int ddf_fp8_act_scales(const ddf_net_desc* d, const void* packed_fp32, const float* rays, int64_t n,
-                       float* act_scales_host, void* ws, size_t ws_bytes, void* stream) {
-  return fail(DDF_ERR_UNSUPPORTED, "fp8 calibration not built yet");
-}
-
 }  // extern "C"

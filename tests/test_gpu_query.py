@@ -143,3 +143,99 @@ def test_sphere_trace_planted_box_matches_oracle():
     # a hit point is on the box surface (the planted SDF is exact there)
     p = ro[hit] + t[hit, None] * rd[hit]
     assert np.all(np.abs(box_sdf(p, half)) < 2e-4)
+
+
+def _calib_rays():
+    return I.free_rays(I.scene_mixed(256, 2), 4096, 21)
+
+
+@pytest.mark.parametrize("n_hidden", [2, 3])
+def test_fp8_query_shallow_matches_emulated_oracle(n_hidden):
+    """With one or two e4m3-quantised layers the kernel reproduces the emulation closely.
+
+    Deeper nets cannot be compared this tightly: a float32 accumulation difference that
+    moves one activation across an e4m3 rounding boundary changes it by a whole e4m3 step
+    (6-12 %), and that perturbation flips further roundings in every later layer."""
+    dev = cuda()
+    desc = I.NetDesc(6, 10, n_hidden, 1024, 2)
+    params = I.test_params(desc, 4)
+    scales = np.array(O.act_scales_fp8(desc, params, _calib_rays()), dtype=np.float32)
+    sc = I.scene_mixed(256, 2)
+    rays = I.shadow_rays(sc, 128 * 11 + 57, 14)
+    packed = ddf.pack(desc, "fp8", _t(params, dev), act_scales=scales)
+    t, xi = ddf.query(desc, "fp8", packed, _t(rays, dev))
+    torch.cuda.synchronize()
+    t = t.cpu().numpy().astype(np.float64); xi = xi.cpu().numpy().astype(np.float64)
+    te, xe, _, _ = O.ddf_query_emulated(desc, params, rays, "fp8", act_scales=[float(s) for s in scales])
+    t64, _, _, _ = O.ddf_query(desc, params, rays)
+    d_em = np.abs(t - te)
+    q_err = np.abs(te - t64).mean()
+    print(f"fp8 {n_hidden} layers vs emulated: max {d_em.max():.3g} mean {d_em.mean():.3g}; "
+          f"emulated vs fp64 mean {q_err:.3g}")
+    assert np.all(np.isfinite(t))
+    assert d_em.mean() <= 0.1 * q_err
+    assert np.median(d_em) <= 1e-5 * max(1.0, np.abs(te).max())
+
+
+def test_fp8_query_full_net_tracks_emulated_oracle():
+    dev = cuda()
+    desc = I.NET_FULL
+    params = I.test_params(desc, 4)
+    scales = np.array(O.act_scales_fp8(desc, params, _calib_rays()), dtype=np.float32)
+    sc = I.scene_mixed(256, 2)
+    rays = I.shadow_rays(sc, 128 * 11 + 57, 14)
+    packed = ddf.pack(desc, "fp8", _t(params, dev), act_scales=scales)
+    t, xi = ddf.query(desc, "fp8", packed, _t(rays, dev))
+    torch.cuda.synchronize()
+    t = t.cpu().numpy().astype(np.float64)
+    te, _, _, _ = O.ddf_query_emulated(desc, params, rays, "fp8", act_scales=[float(s) for s in scales])
+    t64, _, _, _ = O.ddf_query(desc, params, rays)
+    d_em = np.abs(t - te)
+    q_err = np.abs(te - t64).mean()
+    print(f"fp8 12x1024 vs emulated: max {d_em.max():.3g} mean {d_em.mean():.3g}; emulated vs fp64 mean {q_err:.3g}")
+    assert np.all(np.isfinite(t))
+    assert d_em.mean() <= 0.75 * q_err
+
+
+def test_fp8_calibration_matches_oracle():
+    dev = cuda()
+    desc = I.NET_FULL
+    params = I.test_params(desc, 4)
+    calib = _calib_rays()
+    ref = O.act_scales_fp8(desc, params, calib)
+    packed32 = ddf.pack(desc, "fp32", _t(params, dev))
+    got = ddf.fp8_act_scales(desc, packed32, _t(calib, dev))
+    np.testing.assert_array_equal(got, np.array(ref, dtype=np.float32))
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_reduced_precision_vs_fp64_ao_workload(precision):
+    """AO workload (surface points x 32 cosine rays): |dt| and visibility flips vs float64.
+
+    The kernel's error must be of the size the format's own rounding implies: at most
+    1.5x the emulated oracle's mean |dt| and flip rate against float64 (plus a small
+    floor), and within the absolute gates mean |dt| <= 1e-2 (bf16) / 5e-2 (fp8)."""
+    dev = cuda()
+    desc = I.NET_FULL
+    params = I.he_init(desc, 0)
+    sc = I.scene_mixed(256, 2)
+    rays = I.ao_rays(sc, 96, 32, 13)          # 3072 rays
+    scales = None
+    if precision == "fp8":
+        scales = O.act_scales_fp8(desc, params, _calib_rays())
+    packed = ddf.pack(desc, precision, _t(params, dev),
+                      act_scales=None if scales is None else np.array(scales, dtype=np.float32))
+    t, xi = ddf.query(desc, precision, packed, _t(rays, dev))
+    torch.cuda.synchronize()
+    t = t.cpu().numpy().astype(np.float64); xi = xi.cpu().numpy().astype(np.float64)
+    t64, x64, _, zx = O.ddf_query(desc, params, rays)
+    te, xe, _, _ = O.ddf_query_emulated(desc, params, rays, precision, act_scales=scales)
+    dt = np.abs(t - t64)
+    flips = ((xi > 0.5) != (x64 > 0.5)).mean()
+    e_dt = np.abs(te - t64).mean()
+    e_flips = ((xe > 0.5) != (x64 > 0.5)).mean()
+    print(f"{precision} vs fp64 on AO rays: max|dt| {dt.max():.3g} mean {dt.mean():.3g} flip rate {flips:.4f}; "
+          f"emulated: mean {e_dt:.3g} flips {e_flips:.4f}")
+    assert dt.mean() <= 1.5 * e_dt + 1e-4
+    assert flips <= 1.5 * e_flips + 2e-3
+    assert dt.mean() <= (1e-2 if precision == "bf16" else 5e-2)
