@@ -305,3 +305,59 @@ def sdf_points(n: int, seed: int) -> np.ndarray:
     """Points uniform in the object box as float32 [3, N] (SDF fitting inputs)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.ascontiguousarray(rng.uniform(-BOX_HALF, BOX_HALF, (3, n)).astype(np.float32))
+
+
+def planted_box_sdf(desc, half, seed, bias=1.0, noise=0.05):
+    """SDF MLP (n_in = 3, n_out = 1, n_hidden >= 5) that computes max_i(|p_i| - half_i) exactly.
+
+    The first 14 neurons of each layer carry the computation through ReLUs; every other
+    neuron gets random weights and biases (so the products are dense) but feeds nothing
+    the planted path reads.  The value is a lower bound of the distance to the box
+    [-half, half] outside it, so it is a valid function to sphere trace."""
+    assert desc.n_in == 3 and desc.n_out == 1 and desc.n_hidden >= 5
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = rng.standard_normal(desc.param_count()) * noise
+    views = split_params(desc, p)
+    B = bias
+    # layer 1: relu(+p_i), relu(-p_i)
+    W, b = views[0]
+    W[:14, :] = 0.0; b[:14] = 0.0
+    for i in range(3):
+        W[2 * i, i] = 1.0; W[2 * i + 1, i] = -1.0
+    # layer 2: u_i = relu(|p_i| - half_i + B)
+    W, b = views[1]
+    W[:14, :] = 0.0; b[:14] = 0.0
+    for i in range(3):
+        W[i, 2 * i] = 1.0; W[i, 2 * i + 1] = 1.0; b[i] = B - half[i]
+    # layer 3: m = relu(u_y - u_x), pass u_x, u_z
+    W, b = views[2]
+    W[:14, :] = 0.0; b[:14] = 0.0
+    W[0, 1] = 1.0; W[0, 0] = -1.0
+    W[1, 0] = 1.0
+    W[2, 2] = 1.0
+    # layer 4: v = u_x + m = max(u_x, u_y); pass u_z
+    W, b = views[3]
+    W[:14, :] = 0.0; b[:14] = 0.0
+    W[0, 0] = 1.0; W[0, 1] = 1.0
+    W[1, 2] = 1.0
+    # layer 5: w = relu(u_z - v), pass v
+    W, b = views[4]
+    W[:14, :] = 0.0; b[:14] = 0.0
+    W[0, 1] = 1.0; W[0, 0] = -1.0
+    W[1, 0] = 1.0
+    # layers 6..n: s + B = v + w in neuron 0, passed through
+    for l in range(5, desc.n_hidden):
+        W, b = views[l]
+        W[:14, :] = 0.0; b[:14] = 0.0
+        if l == 5:
+            W[0, 0] = 1.0; W[0, 1] = 1.0
+        else:
+            W[0, 0] = 1.0
+    Wh, bh = views[-1]
+    Wh[:] = 0.0
+    if desc.n_hidden == 5:
+        Wh[0, 0] = 1.0; Wh[0, 1] = 1.0
+    else:
+        Wh[0, 0] = 1.0
+    bh[0] = -B
+    return p.astype(np.float32)
