@@ -294,6 +294,30 @@ def mlp_backward(desc, params, gamma, dz):
     return np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
 
 
+def mlp_backward_emulated_bf16(desc, params, gamma, dz):
+    """Parameter gradient with the bf16 training path's roundings, exact arithmetic otherwise.
+
+    Forward as mlp_forward_emulated(.., 'bf16'); every stored activation is bf16(h_l)
+    and the stored features are bf16(gamma) (the hi part).  Backward: delta_n =
+    bf16((dz W_head) * 1[h_n > 0]); delta_(l-1) = bf16((delta_l bf16(W_l)) * 1[h_(l-1) > 0]);
+    dW_l = delta_l^T bf16(h_(l-1)) and db_l = sum delta_l over rays; the head gradient
+    reads bf16(h_n)."""
+    L = layers(desc, params)
+    hs, _ = mlp_forward_emulated(desc, params, gamma, 'bf16')
+    ins = [round_bf16(gamma)] + [round_bf16(h) for h in hs]
+    dz = np.asarray(dz, dtype=np.float64)
+    grads = [None] * len(L)
+    Wh, _ = L[-1]
+    grads[-1] = (dz.T @ ins[-1], dz.sum(axis=0))
+    da = round_bf16((dz @ Wh) * (hs[-1] > 0.0))
+    for l in range(len(L) - 2, -1, -1):
+        W, _ = L[l]
+        grads[l] = (da.T @ ins[l], da.sum(axis=0))
+        if l > 0:
+            da = round_bf16((da @ round_bf16(W)) * (hs[l - 1] > 0.0))
+    return np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
+
+
 def ddf_loss_and_grad(desc, params, rays, t_gt, hit, **kw):
     """Distillation loss terms and the flat parameter gradient for one batch."""
     g = encode(rays_to_inputs(rays), desc.n_freq)

@@ -22,6 +22,8 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+void g_err_clear() { g_err[0] = 0; }
+
 int hip_status(hipError_t e, const char* what) {
   if (e == hipSuccess) return DDF_OK;
   return fail(DDF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));

@@ -1,5 +1,6 @@
 // Arguments of the fused forward kernel and its per-mode hooks.
 #pragma once
+#include "ddf_chain.h"
 #include "ddf_internal.h"
 
 namespace ddf {
@@ -53,9 +54,6 @@ __device__ inline void trace_update(const FwdArgs& a, int32_t src, float s) {
     a.next_idx[slot] = src;
   }
 }
-
-// Row of the 32x32 accumulator held in register v by `lane`.
-__device__ inline int acc_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
 
 // Encoded inputs of rays [ray0, ray0 + M) into X[:, 0:k1]; padding columns are zero.
 // Reduced precisions store the bf16 hi part in columns [0, k1_half) and the lo part

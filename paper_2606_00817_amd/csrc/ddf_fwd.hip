@@ -14,113 +14,11 @@
 // reductions in a fixed order), so the heads always read the unrounded last
 // hidden layer.  The sinusoidal encoding is computed in registers into LDS
 // at the start of the tile; it never touches HBM.
-#include "ddf_internal.h"
+#include "ddf_chain.h"
 #include "ddf_fwd.h"
+#include "ddf_internal.h"
 
 namespace ddf {
-
-struct PF32 {
-  using E = float;
-  using AFrag = f32x4;
-  using BFrag = f32x4;
-  static constexpr int M = 32;
-  static constexpr int KBLK = 8;
-  static constexpr int PF = 1;       // weight blocks in flight ahead of the one in use
-  static __device__ inline void mma(f32x16& c, const AFrag& a, const BFrag& b) {
-    // k is permuted inside the block: step s uses k = 4 * (lane / 32) + s
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[0], b[0], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[1], b[1], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[2], b[2], c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_32x32x2f32(a[3], b[3], c, 0, 0, 0);
-  }
-};
-
-struct PBF16 {
-  using E = __bf16;
-  using AFrag = bf16x8;
-  using BFrag = bf16x8;
-  static constexpr int M = 64;
-  static constexpr int KBLK = 16;
-  static constexpr int PF = 1;
-  static __device__ inline void mma(f32x16& c, const AFrag& a, const BFrag& b) {
-    c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
-  }
-};
-
-template <class P, int WIDTH>
-struct Chain {
-  using E = typename P::E;
-  using AFrag = typename P::AFrag;
-  using BFrag = typename P::BFrag;
-  static constexpr int M = P::M;
-  static constexpr int RT = M / 32;                  // 32-ray tiles per workgroup
-  static constexpr int NT = WIDTH / 32 / kWaves;     // 32-neuron tiles per wave
-  static constexpr int LDX = WIDTH + 16 / (int)sizeof(E);  // padded LDS row (elements)
-  static constexpr int PF = P::PF;
-
-  static __device__ inline BFrag load_b(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
-    return __builtin_bit_cast(BFrag, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
-  }
-
-  // acc[rt][t] += X[rt rows][0:K] * W[(nt0 + t) neuron tile][0:K]^T.  The weight blocks of
-  // one layer are read through a buffer resource: per-lane offset lane * 16 bytes, the
-  // block offset ((nt0 + t) KB + k) * 1 KiB is wave-uniform.  Loads run three blocks
-  // ahead in a ring of four; KB is a multiple of 4, and the loads past the end of the
-  // layer are bounds-checked by the buffer resource (they return zeros, never used).
-  template <int KBC>
-  static __device__ inline void gemm(f32x16 (&acc)[RT][NT], const E* X, const void* W, int KB_rt,
-                                     int nt0, int lane) {
-    const int KB = KBC > 0 ? KBC : KB_rt;   // compile-time for the hidden layers: fully unrolled
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, WIDTH * KB * 32, 0x00020000);
-    const int voff = lane * 16;
-    const int base = nt0 * KB * 1024;
-    const int tstride = KB * 1024;
-    const E* xrow = X + (lane & 31) * LDX + (P::KBLK / 2) * (lane >> 5);
-    BFrag b0[NT], b1[NT], b2[NT], b3[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      b0[t] = load_b(rs, voff, base + t * tstride);
-      b1[t] = load_b(rs, voff, base + t * tstride + 1024);
-      b2[t] = load_b(rs, voff, base + t * tstride + 2048);
-    }
-#pragma unroll (KBC > 0 ? KBC / 4 : 1)
-    for (int k = 0; k < KB; k += 4) {
-      const int kb = base + k * 1024;
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b3[t] = load_b(rs, voff, kb + t * tstride + 3 * 1024);
-      __builtin_amdgcn_sched_barrier(0);
-      step(acc, xrow, k, b0);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b0[t] = load_b(rs, voff, kb + t * tstride + 4 * 1024);
-      __builtin_amdgcn_sched_barrier(0);
-      step(acc, xrow, k + 1, b1);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b1[t] = load_b(rs, voff, kb + t * tstride + 5 * 1024);
-      __builtin_amdgcn_sched_barrier(0);
-      step(acc, xrow, k + 2, b2);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) b2[t] = load_b(rs, voff, kb + t * tstride + 6 * 1024);
-      __builtin_amdgcn_sched_barrier(0);
-      step(acc, xrow, k + 3, b3);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-  }
-
-  static __device__ inline void step(f32x16 (&acc)[RT][NT], const E* xrow, int k, const BFrag (&b)[NT]) {
-    AFrag av[RT];
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-      av[rt] = *reinterpret_cast<const AFrag*>(xrow + rt * 32 * LDX + k * P::KBLK);
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int t = 0; t < NT; ++t) P::mma(acc[rt][t], av[rt], b[t]);
-  }
-};
 
 template <class P, int WIDTH, int MODE>
 __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
@@ -242,7 +140,7 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
         break;
       case kModeTrain:
         a.out0[g] = z0;
-        a.out1[g] = z1;
+        if (a.n_out > 1) a.out1[g] = z1;
         break;
       case kModeSdf:
         a.out0[g] = z0;

@@ -1,29 +1,645 @@
-// Training path of libddf: kept activations, distillation loss, backward, Adam.
+// Training path of libddf: forward with kept activations, distillation loss,
+// backward through the fused chain, weight gradients, Adam on the fp32 master.
+//
+// Workspace (one training batch of n rays, rows padded to R = n rounded up to 128):
+//   act    [k1_half + n_hidden * width] columns x R rows, [R / 8][cols][8] layout
+//          per slab: the encoded features, then H_1 .. H_n (post-ReLU), operand type
+//   delta  n_hidden slabs [R / 8][width][8]: dL/da_l of every hidden layer
+//   z_t, z_xi, dz_t, dz_xi   fp32 [R] each
+//   loss partials, scalars, and (when the caller passes none) the gradient buffer.
+// Everything is deterministic: no floating-point atomics; every reduction has a
+// fixed order.
+#include "ddf_chain.h"
 #include "ddf_fwd.h"
 #include "ddf_train.h"
+
+namespace ddf {
+
+constexpr int kLossBlocks = 256;
+
+struct TrainWs {
+  int64_t R;                // padded rows
+  int64_t act, delta;       // byte offsets of the two stores
+  int64_t zt, zx, dzt, dzx; // fp32 [R]
+  int64_t lossp;            // [kLossBlocks][8] floats
+  int64_t scal;             // 64 bytes of scalars
+  int64_t grad;             // fp32 [P] (used when the caller passes no gradient buffer)
+  int64_t total;
+  int esize;
+};
+
+inline TrainWs train_ws(const ddf_net_desc& d, int64_t batch, size_t nparams) {
+  const Layout L = make_layout(d);
+  TrainWs w{};
+  w.esize = d.precision == DDF_FP32 ? 4 : 2;
+  w.R = (batch + 127) / 128 * 128;
+  int64_t off = 0;
+  w.act = off; off = align256(off + ((int64_t)L.k1_half + (int64_t)d.n_hidden * d.width) * w.R * w.esize);
+  w.delta = off; off = align256(off + (int64_t)d.n_hidden * d.width * w.R * w.esize);
+  w.zt = off; off = align256(off + 4 * w.R);
+  w.zx = off; off = align256(off + 4 * w.R);
+  w.dzt = off; off = align256(off + 4 * w.R);
+  w.dzx = off; off = align256(off + 4 * w.R);
+  w.lossp = off; off = align256(off + 32ll * kLossBlocks);
+  w.scal = off; off = align256(off + 64);
+  w.grad = off; off = align256(off + 4 * (int64_t)nparams);
+  w.total = off;
+  return w;
+}
+
+// Float offsets of every layer's weight and bias in the master vector.
+struct MasterOffsets {
+  int64_t w[kMaxLayers + 1], b[kMaxLayers + 1];
+};
+
+inline MasterOffsets master_offsets(const ddf_net_desc& d) {
+  MasterOffsets m{};
+  const int64_t nf = (int64_t)d.n_in * (1 + 2 * d.n_freq);
+  int64_t off = 0;
+  for (int l = 0; l < d.n_hidden; ++l) {
+    const int64_t fi = l == 0 ? nf : d.width;
+    m.w[l] = off; off += fi * d.width;
+    m.b[l] = off; off += d.width;
+  }
+  m.w[d.n_hidden] = off; off += (int64_t)d.n_out * d.width;
+  m.b[d.n_hidden] = off;
+  return m;
+}
+
+// ------------------------------------------------------------------ loss
+
+// Neumaier compensated accumulation: s + c carries the running sum.
+__device__ inline void kahan_add(float& s, float& c, float x) {
+  const float t = s + x;
+  c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+  s = t;
+}
+
+struct LossArgs {
+  const float* zt; const float* zx; const float* tgt; const uint8_t* hit;
+  int64_t n, R;
+  float* partial;     // [kLossBlocks][8]
+  float* scal;        // [0] 1 / n_hit, [1] n_hit
+  float* loss_out;    // [3] total, l1, bce
+  float* dzt; float* dzx;
+  float bce_weight, clamp;
+};
+
+// Per-block compensated sums of the L1 term, the BCE term and the hit count.
+__global__ void loss_partial_kernel(LossArgs a) {
+  float l1 = 0.f, l1c = 0.f, bce = 0.f, bcec = 0.f, hits = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)kLossBlocks * blockDim.x) {
+    const float y = a.hit[i] ? 1.f : 0.f;
+    const float z = a.zx[i];
+    kahan_add(bce, bcec, softplusf_(z) - y * z);
+    if (a.hit[i]) {
+      const float u = fabsf(softplusf_(a.zt[i]) - a.tgt[i]);
+      kahan_add(l1, l1c, u != u ? u : fminf(u, a.clamp));   // a NaN error stays NaN
+      hits += 1.f;
+    }
+  }
+  __shared__ float red[kThreads][5];
+  red[threadIdx.x][0] = l1; red[threadIdx.x][1] = l1c;
+  red[threadIdx.x][2] = bce; red[threadIdx.x][3] = bcec; red[threadIdx.x][4] = hits;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s0 = 0.f, c0 = 0.f, s1 = 0.f, c1 = 0.f, h = 0.f;
+    for (int t = 0; t < kThreads; ++t) {      // fixed order
+      kahan_add(s0, c0, red[t][0]); c0 += red[t][1];
+      kahan_add(s1, c1, red[t][2]); c1 += red[t][3];
+      h += red[t][4];
+    }
+    float* p = a.partial + blockIdx.x * 8;
+    p[0] = s0; p[1] = c0; p[2] = s1; p[3] = c1; p[4] = h;
+  }
+}
+
+__global__ void loss_final_kernel(LossArgs a) {
+  if (threadIdx.x != 0) return;
+  float s0 = 0.f, c0 = 0.f, s1 = 0.f, c1 = 0.f, h = 0.f;
+  for (int b = 0; b < kLossBlocks; ++b) {
+    const float* p = a.partial + b * 8;
+    kahan_add(s0, c0, p[0]); c0 += p[1];
+    kahan_add(s1, c1, p[2]); c1 += p[3];
+    h += p[4];
+  }
+  const float l1 = h > 0.f ? (s0 + c0) / h : 0.f;
+  const float bce = a.n > 0 ? (s1 + c1) / (float)a.n : 0.f;
+  a.scal[0] = h > 0.f ? 1.f / h : 0.f;
+  a.scal[1] = h;
+  if (a.loss_out) {
+    a.loss_out[0] = l1 + a.bce_weight * bce;
+    a.loss_out[1] = l1;
+    a.loss_out[2] = bce;
+  }
+}
+
+// Per-ray logit gradients; rows n..R-1 get zeros.
+__global__ void loss_grad_kernel(LossArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.R) return;
+  float gt = 0.f, gx = 0.f;
+  if (i < a.n) {
+    const float inv_hit = a.scal[0];
+    const float y = a.hit[i] ? 1.f : 0.f;
+    if (a.hit[i]) {
+      const float u = softplusf_(a.zt[i]) - a.tgt[i];
+      const float sgn = u > 0.f ? 1.f : (u < 0.f ? -1.f : 0.f);
+      if (u != u) gt = u;                                   // NaN: poison the step
+      else if (fabsf(u) <= a.clamp) gt = sgn * sigmoidf_(a.zt[i]) * inv_hit;
+    }
+    gx = a.bce_weight * (sigmoidf_(a.zx[i]) - y) / (float)a.n;
+  }
+  a.dzt[i] = gt;
+  a.dzx[i] = gx;
+}
+
+__global__ void copy_grads_kernel(const float* gzt, const float* gzx, float* dzt, float* dzx, int64_t n, int64_t R) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R) return;
+  dzt[i] = i < n ? gzt[i] : 0.f;
+  dzx[i] = (i < n && gzx) ? gzx[i] : 0.f;
+}
+
+// ------------------------------------------------------------------ backward chain
+
+struct BwdArgs {
+  const uint8_t* packed;
+  Layout lay;
+  int n_hidden, n_out;
+  int64_t R;
+  const void* act;
+  void* delta;
+  const float* dzt;
+  const float* dzx;
+};
+
+// delta_n = (dz_t w_t + dz_xi w_xi) * 1[H_n > 0]; then for l = n..2:
+// delta_(l-1) = (delta_l W_l) * 1[H_(l-1) > 0], the product on the matrix cores with the
+// transposed weight blocks, the running delta resident in LDS.  Every delta_l is stored.
+template <class P, int WIDTH>
+__global__ __launch_bounds__(kThreads, 1) void bwd_chain_kernel(BwdArgs a) {
+  using C = Chain<P, WIDTH>;
+  using E = typename P::E;
+  constexpr int M = C::M, RT = C::RT, NT = C::NT, LDX = C::LDX;
+  __shared__ __attribute__((aligned(16))) E X[M * LDX];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t ray0 = (int64_t)blockIdx.x * M;
+  const E* act = reinterpret_cast<const E*>(a.act);
+  E* delta = reinterpret_cast<E*>(a.delta);
+  const int64_t slab = (int64_t)WIDTH * a.R;
+  const E* H = act + (int64_t)a.lay.k1_half * a.R;      // H_1 slab; H_l at (l - 1) * slab
+  const float* hw = reinterpret_cast<const float*>(a.packed + a.lay.head_w_off);
+
+  {
+    const E* Hn = H + (int64_t)(a.n_hidden - 1) * slab;
+    E* Dn = delta + (int64_t)(a.n_hidden - 1) * slab;
+    for (int idx = threadIdx.x; idx < M * WIDTH; idx += kThreads) {
+      const int q = idx & 7;
+      const int j = (idx >> 3) % WIDTH;
+      const int rb = (idx >> 3) / WIDTH;
+      const int64_t g = ray0 + rb * 8 + q;
+      const int64_t gi = act_index(g, j, WIDTH);
+      float d = a.dzt[g] * hw[j];
+      if (a.n_out > 1) d = fmaf(a.dzx[g], hw[WIDTH + j], d);
+      d = (float)Hn[gi] > 0.f ? d : 0.f;
+      X[(rb * 8 + q) * LDX + j] = (E)d;
+      Dn[gi] = (E)d;
+    }
+  }
+  __syncthreads();
+  const int nt0 = wave * NT;
+  for (int l = a.n_hidden - 1; l >= 1; --l) {
+    f32x16 acc[RT][NT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
+    C::template gemm<WIDTH / P::KBLK>(acc, X, a.packed + a.lay.wt_off[l], WIDTH / P::KBLK, nt0, lane);
+    __syncthreads();
+    const E* Hm = H + (int64_t)(l - 1) * slab;        // H_(l-1): output of hidden layer l - 1
+    E* Dm = delta + (int64_t)(l - 1) * slab;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int n = (nt0 + t) * 32 + (lane & 31);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t g0 = ray0 + rt * 32 + 8 * q;
+          const int64_t gi = ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int v = 4 * q + i;
+            const float d = (float)Hm[gi + i] > 0.f ? acc[rt][t][v] : 0.f;
+            X[(rt * 32 + acc_row(v, lane)) * LDX + n] = (E)d;
+            Dm[gi + i] = (E)d;
+          }
+        }
+      }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ weight gradients
+
+struct DwArgs {
+  const uint8_t* act;     // features slab then H_1..H_n
+  const uint8_t* delta;   // delta_1..delta_n
+  float* grad;
+  MasterOffsets mo;
+  int64_t R;
+  int n_hidden, width, k1_half, n_feat;
+  int tiles_l0, tiles_l;  // workgroups for layer 1 and for every other hidden layer
+  int tn_l0;              // column tiles of layer 1
+};
+
+// dW_l = sum_rays delta_l^T H_(l-1) (H_0 = the encoded features) and db_l = sum_rays delta_l,
+// for every hidden layer in one launch.  A workgroup owns a TM x 128 tile of one layer's
+// gradient and runs over all R rays: 4 waves in 2 x 2, each (TM/2) x 64, operands read in
+// matrix-core order straight from the [R / 8][cols][8] stores.  No split over rays, so
+// every sum has one fixed order.
+template <class P, int TM>
+__global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
+  using E = typename P::E;
+  using Frag = typename P::AFrag;
+  constexpr int RTW = TM / 64;   // 32-row tiles per wave
+  constexpr int KB = P::KBLK;    // rays per step
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int blk = blockIdx.x;
+  int layer, tm, tn, cols;
+  if (blk < a.tiles_l0) {
+    layer = 0; cols = a.k1_half;
+    tm = blk / a.tn_l0; tn = blk % a.tn_l0;
+  } else {
+    blk -= a.tiles_l0;
+    layer = 1 + blk / a.tiles_l; blk %= a.tiles_l;
+    cols = a.width;
+    const int tnl = a.width / 128;
+    tm = blk / tnl; tn = blk % tnl;
+  }
+  const int W = a.width;
+  const int row0 = tm * TM + (wave >> 1) * (TM / 2);
+  const int col0 = tn * 128 + (wave & 1) * 64;
+  const int64_t es = sizeof(E);
+  const uint8_t* D = a.delta + (int64_t)layer * W * a.R * es;
+  const uint8_t* Hb = layer == 0 ? a.act : a.act + ((int64_t)a.k1_half + (int64_t)(layer - 1) * W) * a.R * es;
+  const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(D), (short)0,
+                                                                      (int)(W * a.R * es), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(Hb), (short)0,
+                                                                      (int)(cols * a.R * es), 0x00020000);
+  // lane's byte offset inside a step: bf16 steps cover 16 rays (two 8-ray blocks, one per
+  // lane half), fp32 steps 8 rays (one block, 4 rays per lane half)
+  const int half = lane >> 5;
+  auto a_off = [&](int row) { return es == 2 ? (half * W + row) * 16 : row * 32 + half * 16; };
+  auto b_off = [&](int col) { return es == 2 ? (half * cols + col) * 16 : col * 32 + half * 16; };
+  const int a_step = W * 8 * (int)es * (KB / 8) ;     // bytes per step in the delta store
+  const int b_step = cols * 8 * (int)es * (KB / 8);
+  int ao[RTW], bo[2];
+#pragma unroll
+  for (int r = 0; r < RTW; ++r) ao[r] = a_off(row0 + r * 32 + (lane & 31));
+#pragma unroll
+  for (int c = 0; c < 2; ++c) bo[c] = b_off(col0 + c * 32 + (lane & 31));
+
+  f32x16 acc[RTW][2];
+#pragma unroll
+  for (int r = 0; r < RTW; ++r) { acc[r][0] = f32x16{}; acc[r][1] = f32x16{}; }
+  float rsum[RTW];
+#pragma unroll
+  for (int r = 0; r < RTW; ++r) rsum[r] = 0.f;
+  const bool do_bias = (tn == 0) && ((wave & 1) == 0);
+
+  const int steps = (int)(a.R / KB);
+  Frag A0[RTW], B0[2], A1[RTW], B1[2];
+#pragma unroll
+  for (int r = 0; r < RTW; ++r) A0[r] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rd, ao[r], 0, 0));
+#pragma unroll
+  for (int c = 0; c < 2; ++c) B0[c] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rh, bo[c], 0, 0));
+  for (int s = 0; s < steps; s += 2) {
+    const int sa1 = (s + 1) * a_step, sb1 = (s + 1) * b_step;
+#pragma unroll
+    for (int r = 0; r < RTW; ++r) A1[r] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rd, ao[r], sa1, 0));
+#pragma unroll
+    for (int c = 0; c < 2; ++c) B1[c] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rh, bo[c], sb1, 0));
+#pragma unroll
+    for (int r = 0; r < RTW; ++r) {
+      P::mma(acc[r][0], A0[r], B0[0]);
+      P::mma(acc[r][1], A0[r], B0[1]);
+      if (do_bias)
+#pragma unroll
+        for (int j = 0; j < KB / 2; ++j) rsum[r] += (float)A0[r][j];
+    }
+    const int sa2 = (s + 2) * a_step, sb2 = (s + 2) * b_step;
+#pragma unroll
+    for (int r = 0; r < RTW; ++r) A0[r] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rd, ao[r], sa2, 0));
+#pragma unroll
+    for (int c = 0; c < 2; ++c) B0[c] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rh, bo[c], sb2, 0));
+#pragma unroll
+    for (int r = 0; r < RTW; ++r) {
+      P::mma(acc[r][0], A1[r], B1[0]);
+      P::mma(acc[r][1], A1[r], B1[1]);
+      if (do_bias)
+#pragma unroll
+        for (int j = 0; j < KB / 2; ++j) rsum[r] += (float)A1[r][j];
+    }
+  }
+
+  const int fan_in = layer == 0 ? a.n_feat : W;
+  float* gw = a.grad + a.mo.w[layer];
+#pragma unroll
+  for (int r = 0; r < RTW; ++r)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int col = col0 + c * 32 + (lane & 31);
+      if (col < fan_in) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = row0 + r * 32 + acc_row(v, lane);
+          gw[(int64_t)row * fan_in + col] = acc[r][c][v];
+        }
+      }
+    }
+  if (do_bias) {
+    float* gb = a.grad + a.mo.b[layer];
+#pragma unroll
+    for (int r = 0; r < RTW; ++r) {
+      const float tot = rsum[r] + __shfl_xor(rsum[r], 32);   // the two lane halves hold disjoint rays
+      if (lane < 32) gb[row0 + r * 32 + lane] = tot;
+    }
+  }
+}
+
+// Head gradients: dW_head[o][j] = sum_r dz_o[r] H_n[r][j], db_head[o] = sum_r dz_o[r].
+template <class E>
+__global__ void head_grad_kernel(const E* Hn, const float* dzt, const float* dzx, int64_t R, int W, int n_out,
+                                 float* gW, float* gb) {
+  __shared__ float red[8][32][2];
+  const int j = blockIdx.x * 32 + (threadIdx.x & 31);
+  const int grp = threadIdx.x >> 5;
+  float s0 = 0.f, c0 = 0.f, s1 = 0.f, c1 = 0.f;
+  if (blockIdx.x * 32 < W) {
+    for (int64_t rb = grp; rb < R / 8; rb += 8) {
+      const E* h = Hn + (rb * W + j) * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float hv = (float)h[q];
+        kahan_add(s0, c0, dzt[rb * 8 + q] * hv);
+        kahan_add(s1, c1, dzx[rb * 8 + q] * hv);
+      }
+    }
+    red[grp][threadIdx.x & 31][0] = s0 + c0;
+    red[grp][threadIdx.x & 31][1] = s1 + c1;
+  }
+  __syncthreads();
+  if (blockIdx.x * 32 < W && grp == 0) {
+    float t0 = 0.f, t1 = 0.f;
+    for (int g = 0; g < 8; ++g) { t0 += red[g][threadIdx.x][0]; t1 += red[g][threadIdx.x][1]; }
+    gW[j] = t0;
+    if (n_out > 1) gW[W + j] = t1;
+  }
+  if (blockIdx.x == gridDim.x - 1) {      // the extra block: head biases
+    __shared__ float rb2[kThreads][2];
+    float a0 = 0.f, a0c = 0.f, a1 = 0.f, a1c = 0.f;
+    for (int64_t i = threadIdx.x; i < R; i += kThreads) {
+      kahan_add(a0, a0c, dzt[i]);
+      kahan_add(a1, a1c, dzx[i]);
+    }
+    rb2[threadIdx.x][0] = a0 + a0c;
+    rb2[threadIdx.x][1] = a1 + a1c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float t0 = 0.f, t1 = 0.f, u0 = 0.f, u1 = 0.f;
+      for (int t = 0; t < kThreads; ++t) { kahan_add(t0, u0, rb2[t][0]); kahan_add(t1, u1, rb2[t][1]); }
+      gb[0] = t0 + u0;
+      if (n_out > 1) gb[1] = t1 + u1;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ Adam
+
+__global__ void zero_flag_kernel(int32_t* flag) { if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0; }
+
+__global__ void finite_check_kernel(const float* g, int64_t n, int32_t* flag) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(g[i]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+__global__ void adam_kernel(float* p, float* m, float* v, const float* g, int64_t n, const int32_t* flag,
+                            float lr, float b1, float b2, float eps, float bc1, float bc2) {
+  if (*flag) return;                     // a non-finite gradient: the whole update is skipped
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / bc1;
+    const float vh = vi / bc2;
+    p[i] -= lr * mh / (sqrtf(vh) + eps);
+  }
+}
+
+// ------------------------------------------------------------------ host side
+
+static int check_train_desc(const ddf_net_desc* d) {
+  int rc;
+  if ((rc = check_desc(d))) return rc;
+  if (d->precision == DDF_FP8_E4M3) return fail(DDF_ERR_UNSUPPORTED, "training runs in fp32 or bf16");
+  return DDF_OK;
+}
+
+// One activation slab is addressed with 32-bit buffer offsets.
+static int check_rows(const ddf_net_desc& d, const TrainWs& w) {
+  if ((int64_t)d.width * w.R * w.esize >= (1ll << 31))
+    return fail(DDF_ERR_UNSUPPORTED, "batch too large: one activation slab must stay below 2 GiB");
+  return DDF_OK;
+}
+
+static size_t param_count_of(const ddf_net_desc& d) {
+  const size_t nf = (size_t)d.n_in * (1 + 2 * d.n_freq);
+  const size_t w = d.width;
+  return w * nf + w + (size_t)(d.n_hidden - 1) * (w * w + w) + (size_t)d.n_out * w + d.n_out;
+}
+
+template <class P>
+static hipError_t launch_bwd(const ddf_net_desc& d, const BwdArgs& b, hipStream_t st) {
+  const unsigned blocks = (unsigned)(b.R / P::M);
+  switch (d.width) {
+    case 128: hipLaunchKernelGGL((bwd_chain_kernel<P, 128>), dim3(blocks), dim3(kThreads), 0, st, b); break;
+    case 256: hipLaunchKernelGGL((bwd_chain_kernel<P, 256>), dim3(blocks), dim3(kThreads), 0, st, b); break;
+    case 512: hipLaunchKernelGGL((bwd_chain_kernel<P, 512>), dim3(blocks), dim3(kThreads), 0, st, b); break;
+    default: hipLaunchKernelGGL((bwd_chain_kernel<P, 1024>), dim3(blocks), dim3(kThreads), 0, st, b); break;
+  }
+  return hipGetLastError();
+}
+
+template <class P>
+static hipError_t launch_dw(const ddf_net_desc& d, DwArgs& a, hipStream_t st) {
+  const int TM = d.width >= 256 ? 256 : 128;
+  a.tn_l0 = (a.k1_half + 127) / 128;
+  a.tiles_l0 = (d.width / TM) * a.tn_l0;
+  a.tiles_l = (d.width / TM) * (d.width / 128);
+  const unsigned blocks = (unsigned)(a.tiles_l0 + (d.n_hidden - 1) * a.tiles_l);
+  if (TM == 256)
+    hipLaunchKernelGGL((dw_kernel<P, 256>), dim3(blocks), dim3(kThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL((dw_kernel<P, 128>), dim3(blocks), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+// Backward from the logit gradients already in ws (dz_t, dz_xi) into grad.
+static int run_backward(const ddf_net_desc& d, const void* packed, const TrainWs& w, uint8_t* ws, float* grad,
+                        hipStream_t st) {
+  const Layout L = make_layout(d);
+  BwdArgs b{};
+  b.packed = static_cast<const uint8_t*>(packed);
+  b.lay = L;
+  b.n_hidden = d.n_hidden; b.n_out = d.n_out; b.R = w.R;
+  b.act = ws + w.act; b.delta = ws + w.delta;
+  b.dzt = reinterpret_cast<const float*>(ws + w.dzt);
+  b.dzx = reinterpret_cast<const float*>(ws + w.dzx);
+  hipError_t e = d.precision == DDF_FP32 ? launch_bwd<PF32>(d, b, st) : launch_bwd<PBF16>(d, b, st);
+  if (e != hipSuccess) return hip_status(e, "backward chain launch");
+  DwArgs a{};
+  a.act = ws + w.act; a.delta = ws + w.delta; a.grad = grad;
+  a.mo = master_offsets(d);
+  a.R = w.R; a.n_hidden = d.n_hidden; a.width = d.width; a.k1_half = L.k1_half; a.n_feat = L.n_feat;
+  e = d.precision == DDF_FP32 ? launch_dw<PF32>(d, a, st) : launch_dw<PBF16>(d, a, st);
+  if (e != hipSuccess) return hip_status(e, "weight-gradient launch");
+  const int64_t hslab = ((int64_t)L.k1_half + (int64_t)(d.n_hidden - 1) * d.width) * w.R * w.esize;
+  const unsigned hb = (unsigned)(d.width / 32 + 1);
+  const MasterOffsets mo = master_offsets(d);
+  if (d.precision == DDF_FP32)
+    head_grad_kernel<float><<<hb, kThreads, 0, st>>>(reinterpret_cast<const float*>(ws + w.act + hslab),
+                                                     b.dzt, b.dzx, w.R, d.width, d.n_out, grad + mo.w[d.n_hidden],
+                                                     grad + mo.b[d.n_hidden]);
+  else
+    head_grad_kernel<__bf16><<<hb, kThreads, 0, st>>>(reinterpret_cast<const __bf16*>(ws + w.act + hslab),
+                                                      b.dzt, b.dzx, w.R, d.width, d.n_out, grad + mo.w[d.n_hidden],
+                                                      grad + mo.b[d.n_hidden]);
+  return hip_status(hipGetLastError(), "head-gradient launch");
+}
+
+static int run_forward_train(const ddf_net_desc& d, const void* packed, const float* rays, int64_t n, float* zt,
+                             float* zx, const TrainWs& w, uint8_t* ws, hipStream_t st) {
+  FwdArgs a{};
+  a.packed = static_cast<const uint8_t*>(packed);
+  a.lay = make_layout(d);
+  a.n_in = d.n_in; a.n_freq = d.n_freq; a.n_hidden = d.n_hidden; a.n_out = d.n_out;
+  a.in = rays; a.n = n; a.stride = n; a.mode = kModeTrain;
+  a.out0 = zt; a.out1 = zx;
+  a.act = ws + w.act; a.act_rows = w.R;
+  return hip_status(launch_forward(d, a, n, st), "training forward launch");
+}
+
+}  // namespace ddf
 
 using namespace ddf;
 
 extern "C" {
 
-size_t ddf_train_workspace_bytes(const ddf_net_desc* d, int64_t batch) { return 0; }
-
-int ddf_forward_train(const ddf_net_desc* d, const void* packed, const float* rays, int64_t n,
-                      float* z_t, float* z_xi, void* ws, size_t ws_bytes, void* stream) {
-  return fail(DDF_ERR_UNSUPPORTED, "training not built yet");
+size_t ddf_train_workspace_bytes(const ddf_net_desc* d, int64_t batch) {
+  if (check_train_desc(d) != DDF_OK || batch < 0) return 0;
+  return (size_t)train_ws(*d, batch, param_count_of(*d)).total;
 }
 
-int ddf_backward(const ddf_net_desc* d, const void* packed, const float* rays, int64_t n,
-                 const float* grad_z_t, const float* grad_z_xi, float* grad_params, void* ws,
-                 size_t ws_bytes, void* stream) {
-  return fail(DDF_ERR_UNSUPPORTED, "training not built yet");
+int ddf_forward_train(const ddf_net_desc* d, const void* packed, const float* rays, int64_t n, float* z_t,
+                      float* z_xi, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_train_desc(d))) return rc;
+  if (n < 0 || n > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(packed, "packed")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(z_t, "z_t")) ||
+      (rc = check_ptr(ws, "ws")))
+    return rc;
+  if (d->n_out > 1 && (rc = check_ptr(z_xi, "z_xi"))) return rc;
+  const TrainWs w = train_ws(*d, n, param_count_of(*d));
+  if ((rc = check_rows(*d, w))) return rc;
+  if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
+  return run_forward_train(*d, packed, rays, n, z_t, d->n_out > 1 ? z_xi : z_t, w, static_cast<uint8_t*>(ws),
+                           (hipStream_t)stream);
+}
+
+int ddf_backward(const ddf_net_desc* d, const void* packed, const float* rays, int64_t n, const float* grad_z_t,
+                 const float* grad_z_xi, float* grad_params, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_train_desc(d))) return rc;
+  if (n < 0 || n > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(packed, "packed")) || (rc = check_ptr(grad_z_t, "grad_z_t")) ||
+      (rc = check_ptr(grad_params, "grad_params")) || (rc = check_ptr(ws, "ws")))
+    return rc;
+  if (d->n_out > 1 && (rc = check_ptr(grad_z_xi, "grad_z_xi"))) return rc;
+  const TrainWs w = train_ws(*d, n, param_count_of(*d));
+  if ((rc = check_rows(*d, w))) return rc;
+  if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* wb = static_cast<uint8_t*>(ws);
+  copy_grads_kernel<<<(unsigned)((w.R + 255) / 256), 256, 0, st>>>(grad_z_t, d->n_out > 1 ? grad_z_xi : nullptr,
+                                                                  reinterpret_cast<float*>(wb + w.dzt),
+                                                                  reinterpret_cast<float*>(wb + w.dzx), n, w.R);
+  if ((rc = hip_status(hipGetLastError(), "gradient copy"))) return rc;
+  g_err_clear();
+  return run_backward(*d, packed, w, wb, grad_params, st);
 }
 
 int ddf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* adam_v, void* packed,
                    const float* rays, const float* t_gt, const uint8_t* hit_gt, int64_t batch,
-                   const ddf_train_hparams* hp, float* loss_out, int32_t* nonfinite_flag,
-                   float* grad_out, void* ws, size_t ws_bytes, void* stream) {
-  return fail(DDF_ERR_UNSUPPORTED, "training not built yet");
+                   const ddf_train_hparams* hp, float* loss_out, int32_t* nonfinite_flag, float* grad_out, void* ws,
+                   size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_train_desc(d))) return rc;
+  if (d->n_in != 6 || d->n_out != 2) return fail(DDF_ERR_INVALID_ARG, "ddf_train_step needs a DDF net (n_in 6, n_out 2)");
+  if (!hp) return fail(DDF_ERR_INVALID_ARG, "hp is NULL");
+  if (batch < 1 || batch > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "batch = %lld out of range", (long long)batch);
+  if (hp->step < 1) return fail(DDF_ERR_INVALID_ARG, "step must be >= 1");
+  if (!(hp->lr >= 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) ||
+      !(hp->eps > 0.f) || !(hp->l1_clamp > 0.f) || !(hp->bce_weight >= 0.f))
+    return fail(DDF_ERR_INVALID_ARG, "hyper-parameters out of range");
+  if ((rc = check_ptr(master, "master")) || (rc = check_ptr(adam_m, "adam_m")) || (rc = check_ptr(adam_v, "adam_v")) ||
+      (rc = check_ptr(packed, "packed")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(t_gt, "t_gt")) ||
+      (rc = check_ptr(hit_gt, "hit_gt")) || (rc = check_ptr(loss_out, "loss_out")) ||
+      (rc = check_ptr(nonfinite_flag, "nonfinite_flag")) || (rc = check_ptr(ws, "ws")))
+    return rc;
+  if (grad_out && (rc = check_ptr(grad_out, "grad_out"))) return rc;
+  const size_t P = param_count_of(*d);
+  const TrainWs w = train_ws(*d, batch, P);
+  if ((rc = check_rows(*d, w))) return rc;
+  if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* wb = static_cast<uint8_t*>(ws);
+  float* zt = reinterpret_cast<float*>(wb + w.zt);
+  float* zx = reinterpret_cast<float*>(wb + w.zx);
+  g_err_clear();
+  if ((rc = run_forward_train(*d, packed, rays, batch, zt, zx, w, wb, st))) return rc;
+  LossArgs la{};
+  la.zt = zt; la.zx = zx; la.tgt = t_gt; la.hit = hit_gt; la.n = batch; la.R = w.R;
+  la.partial = reinterpret_cast<float*>(wb + w.lossp);
+  la.scal = reinterpret_cast<float*>(wb + w.scal);
+  la.loss_out = loss_out;
+  la.dzt = reinterpret_cast<float*>(wb + w.dzt);
+  la.dzx = reinterpret_cast<float*>(wb + w.dzx);
+  la.bce_weight = hp->bce_weight; la.clamp = hp->l1_clamp;
+  loss_partial_kernel<<<kLossBlocks, kThreads, 0, st>>>(la);
+  loss_final_kernel<<<1, 64, 0, st>>>(la);
+  loss_grad_kernel<<<(unsigned)((w.R + 255) / 256), 256, 0, st>>>(la);
+  if ((rc = hip_status(hipGetLastError(), "loss launch"))) return rc;
+  float* grad = grad_out ? grad_out : reinterpret_cast<float*>(wb + w.grad);
+  if ((rc = run_backward(*d, packed, w, wb, grad, st))) return rc;
+  zero_flag_kernel<<<1, 64, 0, st>>>(nonfinite_flag);
+  finite_check_kernel<<<1024, 256, 0, st>>>(grad, (int64_t)P, nonfinite_flag);
+  const double bc1 = 1.0 - pow((double)hp->beta1, (double)hp->step);
+  const double bc2 = 1.0 - pow((double)hp->beta2, (double)hp->step);
+  adam_kernel<<<2048, 256, 0, st>>>(master, adam_m, adam_v, grad, (int64_t)P, nonfinite_flag, hp->lr, hp->beta1,
+                                    hp->beta2, hp->eps, (float)bc1, (float)bc2);
+  if ((rc = hip_status(hipGetLastError(), "adam launch"))) return rc;
+  return hip_status(launch_pack(*d, master, nullptr, packed, st, true), "repack launch");
 }
 
 }  // extern "C"

@@ -64,6 +64,29 @@ def fp32_forward_sigma(desc, params, rays):
     return z, np.sqrt(var)
 
 
+def kink_rays(desc, params, rays, k_sigma=8.0):
+    """Rays with a hidden unit whose pre-activation lies within k sigma of 0.
+
+    sigma is the first-order float32 rounding error of that pre-activation (the model
+    of fp32_forward_sigma).  On such a ray float32 and float64 may disagree about the
+    ReLU, which changes that ray's whole gradient row; parity tests give these rays
+    no gradient on both sides."""
+    L = O.layers(desc, params)
+    g = O.encode(O.rays_to_inputs(rays), desc.n_freq)
+    h = g
+    var = (2 * U32 * g) ** 2
+    bad = np.zeros(len(g), dtype=bool)
+    for li, (W, b) in enumerate(L[:-1]):
+        K = W.shape[1]
+        W2 = W * W
+        var = var @ W2.T + U32 ** 2 * (K / 2 + 1) * ((h ** 2) @ W2.T)
+        a = h @ W.T + b
+        bad |= np.any(np.abs(a) < k_sigma * np.sqrt(var) + 1e-30, axis=1)
+        var = var * (a > 0)
+        h = np.maximum(a, 0.0)
+    return bad
+
+
 def cuda():
     import torch
     if not torch.cuda.is_available():

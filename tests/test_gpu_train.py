@@ -1,0 +1,200 @@
+"""Parity of the HIP training path (forward with kept activations, backward, loss, Adam)
+with the float64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ddf_oracle as O
+from oracle import geometry as G
+from paper_2606_00817_amd import ddf
+from paper_2606_00817_amd import inputs as I
+from tests.helpers import cuda, kink_rays
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def _ws(desc, prec, n, dev):
+    return torch.empty(ddf.train_workspace_bytes(desc, prec, n), dtype=torch.uint8, device=dev)
+
+
+def _grad_oracle(desc, params, rays, dzt, dzx):
+    g = O.encode(O.rays_to_inputs(rays), desc.n_freq)
+    return O.mlp_backward(desc, params, g, np.stack([dzt, dzx], axis=1))
+
+
+def _per_layer_errors(desc, g_gpu, g_ref):
+    out = []
+    for (w_off, b_off, o, i) in desc.offsets():
+        for lo, hi in ((w_off, b_off), (b_off, b_off + o)):
+            ref = g_ref[lo:hi]; got = g_gpu[lo:hi].astype(np.float64)
+            scale = max(np.abs(ref).max(), 1e-30)
+            out.append((np.abs(got - ref).max() / scale,
+                        float(got @ ref / max(np.linalg.norm(got) * np.linalg.norm(ref), 1e-300))))
+    return out
+
+
+@pytest.mark.parametrize("desc,n", [(I.NET_TINY, 1000), (I.NetDesc(6, 10, 3, 256, 2), 300),
+                                    (I.NET_FULL, 333)])
+def test_fp32_backward_matches_oracle(desc, n):
+    dev = cuda()
+    params = I.test_params(desc, 11)
+    sc = I.scene_ellipsoids(64, 3)
+    rays = I.train_rays(sc, n, 1001)
+    rng = np.random.default_rng(5)
+    keep = ~kink_rays(desc, params, rays)
+    dzt = (rng.standard_normal(n) / n * keep).astype(np.float32)
+    dzx = (rng.standard_normal(n) / n * keep).astype(np.float32)
+    packed = ddf.pack(desc, "fp32", _t(params, dev))
+    ws = _ws(desc, "fp32", n, dev)
+    zt, zx = ddf.forward_train(desc, "fp32", packed, _t(rays, dev), ws)
+    g = ddf.backward(desc, "fp32", packed, _t(rays, dev), _t(dzt, dev), _t(dzx, dev), ws)
+    torch.cuda.synchronize()
+    _, z64, zt64, zx64 = O.ddf_query(desc, params, rays)
+    np.testing.assert_allclose(zt.cpu().numpy(), zt64, atol=2e-5 * max(1, np.abs(zt64).max()))
+    np.testing.assert_allclose(zx.cpu().numpy(), zx64, atol=2e-5 * max(1, np.abs(zx64).max()))
+    ref = _grad_oracle(desc, params, rays, dzt.astype(np.float64), dzx.astype(np.float64))
+    errs = _per_layer_errors(desc, g.cpu().numpy(), ref)
+    worst = max(e for e, _ in errs)
+    print(f"fp32 backward {desc.n_hidden}x{desc.width}: worst per-block max rel err {worst:.3g} "
+          f"({(~keep).sum()} of {n} rays near a ReLU kink carry no gradient)")
+    assert worst < 1e-4, errs
+
+
+@pytest.mark.parametrize("n_hidden", [3, 12])
+def test_bf16_backward_matches_emulated_oracle(n_hidden):
+    """bf16 gradients against the oracle with the kernel's bf16 rounding points.
+
+    With 3 layers the kernel reproduces the emulation closely.  With 12 layers a float32
+    accumulation difference that moves a value across a bf16 rounding boundary perturbs
+    later pre-activations, a few ReLU masks flip, and each flip changes that ray's
+    gradient in every layer below; the kernel must still be much closer to the emulation
+    than the emulation is to float64 (bf16 itself flips ~0.3 % of the masks, cosine
+    ~0.985 against float64 at 12 x 1024; that is reported, and gated loosely)."""
+    dev = cuda()
+    desc = I.NetDesc(6, 10, n_hidden, 1024, 2)
+    n = 640
+    params = I.test_params(desc, 12)
+    sc = I.scene_ellipsoids(64, 3)
+    rays = I.train_rays(sc, n, 1002)
+    rng = np.random.default_rng(6)
+    dzt = (rng.standard_normal(n) / n).astype(np.float32)
+    dzx = (rng.standard_normal(n) / n).astype(np.float32)
+    packed = ddf.pack(desc, "bf16", _t(params, dev))
+    ws = _ws(desc, "bf16", n, dev)
+    ddf.forward_train(desc, "bf16", packed, _t(rays, dev), ws)
+    g = ddf.backward(desc, "bf16", packed, _t(rays, dev), _t(dzt, dev), _t(dzx, dev), ws)
+    torch.cuda.synchronize()
+    gam = O.encode(O.rays_to_inputs(rays), desc.n_freq)
+    dz = np.stack([dzt, dzx], axis=1).astype(np.float64)
+    em = O.mlp_backward_emulated_bf16(desc, params, gam, dz)
+    ref = _grad_oracle(desc, params, rays, dzt.astype(np.float64), dzx.astype(np.float64))
+    got = g.cpu().numpy().astype(np.float64)
+
+    def cos(a, b):
+        return a @ b / (np.linalg.norm(a) * np.linalg.norm(b))
+
+    def rel(a, b):
+        return np.linalg.norm(a - b) / np.linalg.norm(b)
+    print(f"bf16 backward {n_hidden}x1024: vs emulated cosine {cos(got, em):.6f} rel L2 {rel(got, em):.3g}; "
+          f"vs float64 cosine {cos(got, ref):.5f}; emulated vs float64 rel L2 {rel(em, ref):.3g}")
+    if n_hidden == 3:
+        assert cos(got, em) >= 0.99995 and rel(got, em) <= 1e-2
+        assert min(c for _, c in _per_layer_errors(desc, got, em)) >= 0.9995
+    else:
+        assert rel(got, em) <= 0.5 * rel(em, ref)
+        assert cos(got, ref) >= 0.95
+
+
+def _train_inputs(desc, n, seed):
+    sc = I.scene_ellipsoids(1024, 3)
+    rays = I.train_rays(sc, n, seed)
+    tg, hit, _ = G.intersect_soa(sc, rays)
+    return rays, np.where(hit, tg, 0.0).astype(np.float32), hit.astype(np.uint8)
+
+
+def _hp(step, lr=3e-3):
+    return ddf.TrainHParamsC(lr, 0.9, 0.999, 1e-8, O.BCE_WEIGHT, O.L1_CLAMP, step)
+
+
+@pytest.mark.parametrize("desc,n", [(I.NET_TINY, 777), (I.NetDesc(6, 10, 4, 512, 2), 300)])
+def test_fp32_train_step_matches_oracle(desc, n):
+    dev = cuda()
+    params = I.test_params(desc, 13).astype(np.float32)
+    rays, tg, hit = _train_inputs(desc, n, 1003)
+    P = desc.param_count()
+    m0 = np.zeros(P); v0 = np.zeros(P)
+    master = _t(params, dev); m = _t(m0.astype(np.float32), dev); v = _t(v0.astype(np.float32), dev)
+    packed = ddf.pack(desc, "fp32", master)
+    ws = _ws(desc, "fp32", n, dev)
+    grad = torch.empty(P, dtype=torch.float32, device=dev)
+    loss, flag = ddf.train_step(desc, "fp32", master, m, v, packed, _t(rays, dev), _t(tg, dev), _t(hit, dev),
+                                _hp(1), ws, grad_out=grad)
+    torch.cuda.synchronize()
+    (tot, l1, bce), g64 = O.ddf_loss_and_grad(desc, params, rays, tg, hit)
+    lo = loss.cpu().numpy()
+    assert int(flag.cpu()[0]) == 0
+    np.testing.assert_allclose(lo[:3], [tot, l1, bce], rtol=2e-5)
+    got = grad.cpu().numpy().astype(np.float64)
+    worst = max(e for e, _ in _per_layer_errors(desc, got, g64))
+    assert worst < 2e-4
+    # Adam from the same gradient: compare where the gradient is not tiny (sign decides step 1)
+    p1, m1, v1 = O.adam_step(params, m0, v0, got, 1, 3e-3)
+    np.testing.assert_allclose(m.cpu().numpy(), m1, rtol=1e-5, atol=1e-6 * np.abs(m1).max())
+    np.testing.assert_allclose(v.cpu().numpy(), v1, rtol=1e-4, atol=1e-6 * np.abs(v1).max())
+    big = np.abs(got) > 1e-6 * np.abs(got).max()
+    np.testing.assert_allclose(master.cpu().numpy()[big], p1[big], rtol=0, atol=1e-6)
+    # the packed copy was rebuilt from the new master: a query agrees with the oracle on it
+    t, _ = ddf.query(desc, "fp32", packed, _t(rays[:, :64], dev))
+    t64, _, _, _ = O.ddf_query(desc, master.cpu().numpy(), rays[:, :64])
+    np.testing.assert_allclose(t.cpu().numpy(), t64, atol=1e-4)
+
+
+def test_train_step_is_deterministic_and_trains():
+    dev = cuda()
+    desc = I.NetDesc(6, 10, 4, 256, 2)
+    n = 4096
+    params = I.he_init(desc, 3)
+    rays, tg, hit = _train_inputs(desc, n, 1004)
+    states = []
+    for rep in range(2):
+        master = _t(params, dev)
+        m = torch.zeros_like(master); v = torch.zeros_like(master)
+        packed = ddf.pack(desc, "bf16", master)
+        ws = _ws(desc, "bf16", n, dev)
+        losses = []
+        for s in range(1, 31):
+            loss, flag = ddf.train_step(desc, "bf16", master, m, v, packed, _t(rays, dev), _t(tg, dev),
+                                        _t(hit, dev), _hp(s, 1e-3), ws)
+            losses.append(loss.cpu().numpy()[0])
+        torch.cuda.synchronize()
+        states.append((master.cpu().numpy(), m.cpu().numpy(), v.cpu().numpy(), np.array(losses)))
+    for a, b in zip(states[0], states[1]):
+        np.testing.assert_array_equal(a, b)
+    losses = states[0][3]
+    print(f"bf16 training 30 steps: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.7 * losses[0]
+
+
+def test_nonfinite_gradient_skips_update():
+    dev = cuda()
+    desc = I.NET_TINY
+    n = 512
+    params = I.test_params(desc, 14)
+    rays, tg, hit = _train_inputs(desc, n, 1005)
+    j = int(np.nonzero(hit)[0][0])
+    tg[j] = np.nan                                 # a corrupt target on one hit ray
+    master = _t(params, dev)
+    m = torch.full_like(master, 1e-3); v = torch.full_like(master, 1e-4)
+    packed = ddf.pack(desc, "fp32", master)
+    ws = _ws(desc, "fp32", n, dev)
+    before = [x.clone() for x in (master, m, v)]
+    loss, flag = ddf.train_step(desc, "fp32", master, m, v, packed, _t(rays, dev), _t(tg, dev), _t(hit, dev),
+                                _hp(3), ws)
+    torch.cuda.synchronize()
+    assert int(flag.cpu()[0]) == 1
+    for a, b in zip(before, (master, m, v)):
+        assert torch.equal(a, b)

@@ -392,3 +392,48 @@ def test_paper_constants_fixture():
     # the full-size net is close to the paper's field-size budget
     mb = I.NET_FULL.param_count() * 4 / 1e6
     assert abs(mb - gold["field_size_mb"]["value"]) < 6.0
+
+
+def test_emulated_bf16_backward_matches_brute_force():
+    """The bf16-rounding backward against element-by-element loops using torch's casts."""
+    def bf(x):
+        return float(torch.tensor(x, dtype=torch.float64).to(torch.float32).to(torch.bfloat16).double())
+
+    desc = I.NetDesc(6, 1, 3, 6, 2)
+    params = I.test_params(desc, 8, bias_std=0.2)
+    rays = I.free_rays(I.scene_spheres(4, 1), 3, 5)
+    g = O.encode(O.rays_to_inputs(rays), desc.n_freq)
+    dz = np.random.default_rng(3).standard_normal((3, 2))
+    got = O.mlp_backward_emulated_bf16(desc, params, g, dz)
+    L = O.layers(desc, params)
+    n_l = len(L)
+    acc = [(np.zeros_like(W), np.zeros_like(b)) for W, b in L]
+    for r in range(3):
+        # forward with the kernel's roundings
+        feats = list(g[r])
+        hi = [bf(x) for x in feats]
+        lo = [bf(x - y) for x, y in zip(feats, hi)]
+        W1, b1 = L[0]
+        a = [b1[o] + sum(bf(W1[o, i]) * (hi[i] + lo[i]) for i in range(len(feats))) for o in range(desc.width)]
+        hs = [[max(0.0, x) for x in a]]
+        for W, b in L[1:-1]:
+            a = [b[o] + sum(bf(W[o, i]) * bf(hs[-1][i]) for i in range(desc.width)) for o in range(desc.width)]
+            hs.append([max(0.0, x) for x in a])
+        ins = [[bf(x) for x in feats]] + [[bf(x) for x in h] for h in hs]
+        Wh, _ = L[-1]
+        for o in range(2):
+            for j in range(desc.width):
+                acc[-1][0][o, j] += dz[r, o] * ins[-1][j]
+            acc[-1][1][o] += dz[r, o]
+        d = [bf(sum(dz[r, o] * Wh[o, j] for o in range(2)) * (hs[-1][j] > 0)) for j in range(desc.width)]
+        for l in range(n_l - 2, -1, -1):
+            W, _ = L[l]
+            for o in range(W.shape[0]):
+                for i in range(W.shape[1]):
+                    acc[l][0][o, i] += d[o] * ins[l][i]
+                acc[l][1][o] += d[o]
+            if l > 0:
+                d = [bf(sum(d[o] * bf(W[o, i]) for o in range(W.shape[0])) * (hs[l - 1][i] > 0))
+                     for i in range(W.shape[1])]
+    ref = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in acc])
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14)
