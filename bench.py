@@ -169,8 +169,11 @@ def main():
                       "frac": tf / PEAK_TFLOPS[p], **precision_stats(desc, params_np, rays_np, tp, xp)}
         out["precisions"] = res
 
+    if "train" in legs:
+        out["train"] = train_leg(torch, ddf, I, dev, timer, args.steps)
+
     if "trace" in legs:
-        out["sphere_trace"] = trace_leg(torch, ddf, I, dev, rays, timer, out)
+        out["sphere_trace"] = trace_leg(torch, ddf, I, dev, rays, timer, out, scene)
 
     if "cpu" in legs:
         out["cpu_baseline"] = cpu_oracle_baseline(desc, params_np, rays_np)
@@ -178,29 +181,112 @@ def main():
     print(json.dumps(out))
 
 
-def trace_leg(torch, ddf, I, dev, rays, timer, out):
+def train_flop_per_ray(desc):
+    """Forward + backward (delta chain without layer 1's input gradient) + weight gradients."""
+    fwd = flop_per_ray(desc)
+    dx = 2 * (desc.n_hidden - 1) * desc.width * desc.width + 2 * desc.n_out * desc.width
+    dw = 2 * desc.width * desc.n_feat + 2 * (desc.n_hidden - 1) * desc.width * desc.width + 2 * desc.n_out * desc.width
+    return fwd + dx + dw
+
+
+def train_leg(torch, ddf, I, dev, timer, steps, batch=65536):
+    """One distillation step per timed step: 65,536 rays (half surface-anchored, half free)
+    against 1,024 random ellipsoids, targets by exact ray casting on the GPU; bf16 forward
+    and backward with the fp32 master, then Adam and the repack."""
+    desc = I.NET_FULL
+    scene = I.scene_ellipsoids(1024, 3)
+    prims = torch.from_numpy(ddf.scene_prims(scene)).to(dev)
+    rays = torch.from_numpy(I.train_rays(scene, batch, 1000)).to(dev)
+    t_gt, hit = ddf.cast_targets(prims, rays)
+    t_gt = torch.where(hit > 0, t_gt, torch.zeros_like(t_gt))
+    res = {"batch": batch, "net": "126-1024x12-2", "targets": "exact ray casting, 1024 ellipsoids",
+           "hit_fraction": float(hit.float().mean().item())}
+    fpr = train_flop_per_ray(desc)
+    for prec in ("bf16", "fp32"):
+        master = torch.from_numpy(I.he_init(desc, 0)).to(dev)
+        m = torch.zeros_like(master)
+        v = torch.zeros_like(master)
+        packed = ddf.pack(desc, prec, master)
+        ws = torch.empty(ddf.train_workspace_bytes(desc, prec, batch), dtype=torch.uint8, device=dev)
+        loss = torch.empty(4, dtype=torch.float32, device=dev)
+        flag = torch.empty(4, dtype=torch.int32, device=dev)
+        step = [0]
+
+        def one():
+            step[0] += 1
+            hp = ddf.TrainHParamsC(1e-3, 0.9, 0.999, 1e-8, 0.3, 3.0, step[0])
+            ddf.train_step(desc, prec, master, m, v, packed, rays, t_gt, hit, hp, ws, loss_out=loss, flag=flag)
+        one()
+        torch.cuda.synchronize()
+        l0 = float(loss[0].item())
+        k = max(2, steps // 2) if prec == "bf16" else 2
+        ms = timer.time(one, k)
+        res[prec] = {"ms_per_step": ms, "train_rays_per_s": batch / (ms * 1e-3),
+                     "tflops": fpr * batch / (ms * 1e-3) / 1e12, "loss_first": l0,
+                     "loss_last": float(loss[0].item()), "steps": step[0],
+                     "skipped": int(flag[0].item())}
+    res["flop_per_ray"] = fpr
+    return res
+
+
+def fit_sdf(torch, ddf, I, dev, scene, steps=400, batch=65536, prec="bf16", seed=100):
+    """Fit the 12 x 1024 signed-distance MLP to the scene's analytic distance bound with the
+    library's own fitting step (L1 on the distance, Adam, cosine-decayed lr)."""
+    import math
+    desc = I.NET_SDF
+    prims = torch.from_numpy(ddf.scene_prims(scene)).to(dev)
+    pool = [torch.from_numpy(I.sdf_train_points(scene, batch, 40 + j)).to(dev) for j in range(8)]
+    gts = [ddf.scene_sdf(prims, p) for p in pool]
+    master = torch.from_numpy(I.he_init(desc, seed)).to(dev)
+    m = torch.zeros_like(master)
+    v = torch.zeros_like(master)
+    packed = ddf.pack(desc, prec, master)
+    ws = torch.empty(ddf.train_workspace_bytes(desc, prec, batch), dtype=torch.uint8, device=dev)
+    loss = torch.empty(4, dtype=torch.float32, device=dev)
+    flag = torch.empty(4, dtype=torch.int32, device=dev)
+    lr0, lr1 = 3e-4, 3e-5
+    for s in range(1, steps + 1):
+        lr = lr1 + 0.5 * (lr0 - lr1) * (1 + math.cos(math.pi * (s - 1) / steps))
+        hp = ddf.TrainHParamsC(lr, 0.9, 0.999, 1e-8, 0.0, 1.0, s)
+        j = (s - 1) % len(pool)
+        ddf.sdf_train_step(desc, prec, master, m, v, packed, pool[j], gts[j], hp, ws, loss_out=loss, flag=flag)
+    held = torch.from_numpy(I.sdf_train_points(scene, batch, 99)).to(dev)
+    held_gt = ddf.scene_sdf(prims, held)
+    packed32 = ddf.pack(desc, "fp32", master)
+    err = (ddf.sdf_eval(desc, "fp32", packed32, held) - held_gt).abs()
+    return packed32, {"steps": steps, "batch": batch, "precision": prec, "final_loss": float(loss[0].item()),
+                      "heldout_mean_abs_err": float(err.mean().item()),
+                      "heldout_p90_abs_err": float(err.quantile(0.9).item())}
+
+
+def trace_leg(torch, ddf, I, dev, rays, timer, out, scene):
     """Sphere tracing of a 12 x 1024 signed-distance MLP along the same shadow rays.
 
-    The SDF MLP carries an exact box distance bound (half extents 0.25, 0.35, 0.45)
-    through its ReLU layers, with random weights on every other neuron, so the
-    iteration converges like sphere tracing a real surface."""
+    The SDF MLP is fitted to the scene first (fit_sdf); the trace runs in fp32 with at most
+    128 steps, hit at |s| < 1e-4, miss beyond t = 6."""
     desc = I.NET_SDF
-    params = torch.from_numpy(I.planted_box_sdf(desc, [0.25, 0.35, 0.45], 100)).to(dev)
-    packed = ddf.pack(desc, "fp32", params)
+    packed, fit = fit_sdf(torch, ddf, I, dev, scene)
     n = rays.shape[1]
     ws = torch.empty(int(ddf.lib().sdf_trace_workspace_bytes(n)), dtype=torch.uint8, device=dev)
-    res = {}
     ddf.sphere_trace(desc, "fp32", packed, rays, 128, 1e-4, 6.0, ws=ws)
     torch.cuda.synchronize()
     ms = timer.time(lambda: ddf.sphere_trace(desc, "fp32", packed, rays, 128, 1e-4, 6.0, ws=ws), 1)
     t, hit, steps = ddf.sphere_trace(desc, "fp32", packed, rays, 128, 1e-4, 6.0, ws=ws)
-    st = steps.cpu().numpy()
-    fp32 = out.get("precisions", {}).get("fp32", {}).get("ms")
-    res = {"sdf": "12x1024 MLP with a planted exact box distance bound", "precision": "fp32",
-           "max_steps": 128, "hit_eps": 1e-4, "t_max": 6.0, "ms": ms, "rays_per_s": n / (ms * 1e-3),
-           "mean_steps": float(st.mean()), "p50_steps": float(np.median(st)), "max_steps_used": int(st.max()),
+    prims = torch.from_numpy(ddf.scene_prims(scene)).to(dev)
+    tg, hg = ddf.cast_targets(prims, rays)
+    st = steps.float()
+    prec = out.get("precisions", {})
+    res = {"sdf": "12x1024 SDF MLP (L=10, 63 features) fitted to the scene's distance bound",
+           "fit": fit, "precision": "fp32", "max_steps": 128, "hit_eps": 1e-4, "t_max": 6.0,
+           "ms": ms, "rays_per_s": n / (ms * 1e-3), "mean_steps": float(st.mean().item()),
+           "p50_steps": float(st.median().item()), "max_steps_used": int(steps.max().item()),
+           "unconverged_fraction": float((steps >= 128).float().mean().item() - 0.0),
            "hit_rate": float(hit.float().mean().item()),
-           "ddf_fp32_speedup": (ms / fp32) if fp32 else None}
+           "hit_agreement_vs_exact_cast": float((hit == hg).float().mean().item())}
+    for p in ("fp32", "bf16", "fp8"):
+        msp = prec.get(p, {}).get("ms") if p != out["dtype"] else out["ms_per_step"]
+        if msp:
+            res[f"speedup_vs_ddf_{p}"] = ms / msp
     return res
 
 

@@ -174,11 +174,28 @@ int sdf_eval(const ddf_net_desc* desc, const void* packed, const float* points, 
 /* Exact supervision targets by brute-force ray casting against an analytic union of
  * spheres/ellipsoids (the paper's exact ray-cast supervision source, Sec. III-B).
  *   prims  device float32 [n_prims][16]: center(3), 1/semi-axes(3), R^T row-major(9),
- *          unused(1), where a primitive is {c + R (a * u) : |u| <= 1}.
+ *          min semi-axis(1), where a primitive is {c + R (a * u) : |u| <= 1}.
  *   t_gt   device float32 [n]: first root > 0 over all primitives (+inf on a miss).
  *   hit    device uint8 [n]. */
 int ddf_cast_targets(const float* prims, int32_t n_prims, const float* rays, int64_t n,
                      float* t_gt, uint8_t* hit, void* stream);
+
+/* Signed-distance bound of the same analytic union at points (targets for fitting an SDF
+ * MLP): min over primitives of (|R^T (p - c) / a| - 1) * min(a), exact for spheres and a
+ * lower bound for ellipsoids.  prims as for ddf_cast_targets with slot 15 = min(a).
+ *   points  device float32 [3][n] SoA.   sdf  device float32 [n]. */
+int ddf_scene_sdf(const float* prims, int32_t n_prims, const float* points, int64_t n, float* sdf,
+                  void* stream);
+
+/* One fitting step of an SDF MLP (desc n_in 3, n_out 1) by Adam on the L1 error
+ *   loss = mean over points of |s(p) - sdf_gt(p)|
+ * with the same forward, backward, Adam and repack as ddf_train_step (hp->bce_weight and
+ * hp->l1_clamp are ignored).  points [3][n], sdf_gt [n]; loss_out device float32 [3]
+ * (loss, loss, 0); workspace ddf_train_workspace_bytes(desc, n). */
+int sdf_train_step(const ddf_net_desc* desc, float* master, float* adam_m, float* adam_v, void* packed,
+                   const float* points, const float* sdf_gt, int64_t n, const ddf_train_hparams* hp,
+                   float* loss_out, int32_t* nonfinite_flag, float* grad_out, void* ws, size_t ws_bytes,
+                   void* stream);
 
 #ifdef __cplusplus
 }

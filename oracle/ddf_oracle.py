@@ -327,6 +327,17 @@ def ddf_loss_and_grad(desc, params, rays, t_gt, hit, **kw):
     return terms, grad
 
 
+def sdf_loss_and_grad(desc, params, points, sdf_gt):
+    """Fitting loss of an SDF MLP, mean |s(p) - sdf_gt(p)| (sign(0) = 0), and its gradient."""
+    g = encode(np.asarray(points, dtype=np.float64), desc.n_freq)
+    _, z = mlp_forward(desc, params, g)
+    u = z[:, 0] - np.asarray(sdf_gt, dtype=np.float64)
+    n = len(u)
+    loss = math.fsum(np.abs(u)) / n
+    grad = mlp_backward(desc, params, g, (np.sign(u) / n)[:, None])
+    return loss, grad
+
+
 def adam_step(p, m, v, g, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     """One bias-corrected Adam update (Kingma & Ba, Algorithm 1); returns new (p, m, v)."""
     p = np.asarray(p, dtype=np.float64); m = np.asarray(m, dtype=np.float64)

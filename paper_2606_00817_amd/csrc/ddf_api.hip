@@ -142,6 +142,30 @@ __global__ void cast_kernel(const float* prims, int n_prims, const float* rays, 
   }
 }
 
+__global__ void scene_sdf_kernel(const float* prims, int n_prims, const float* pts, int64_t n, float* out) {
+  extern __shared__ float sp[];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float x0 = 0, x1 = 0, x2 = 0;
+  if (i < n) { x0 = pts[i]; x1 = pts[n + i]; x2 = pts[2 * n + i]; }
+  float best = __builtin_inff();
+  constexpr int kChunk = 256;
+  for (int base = 0; base < n_prims; base += kChunk) {
+    const int cnt = min(kChunk, n_prims - base);
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt * 16; j += blockDim.x) sp[j] = prims[(int64_t)base * 16 + j];
+    __syncthreads();
+    for (int p = 0; p < cnt; ++p) {
+      const float* q = sp + p * 16;
+      const float r0 = x0 - q[0], r1 = x1 - q[1], r2 = x2 - q[2];
+      const float l0 = (q[6] * r0 + q[7] * r1 + q[8] * r2) * q[3];
+      const float l1 = (q[9] * r0 + q[10] * r1 + q[11] * r2) * q[4];
+      const float l2 = (q[12] * r0 + q[13] * r1 + q[14] * r2) * q[5];
+      best = fminf(best, (sqrtf(l0 * l0 + l1 * l1 + l2 * l2) - 1.f) * q[15]);
+    }
+  }
+  if (i < n) out[i] = best;
+}
+
 }  // namespace ddf
 
 using namespace ddf;
@@ -323,6 +347,19 @@ int ddf_cast_targets(const float* prims, int32_t n_prims, const float* rays, int
   cast_kernel<<<(unsigned)((n + 255) / 256), 256, 256 * 16 * sizeof(float), (hipStream_t)stream>>>(
       prims, n_prims, rays, n, t_gt, hit);
   return hip_status(hipGetLastError(), "ddf_cast_targets launch");
+}
+
+int ddf_scene_sdf(const float* prims, int32_t n_prims, const float* points, int64_t n, float* sdf, void* stream) {
+  int rc;
+  if (n_prims < 1) return fail(DDF_ERR_INVALID_ARG, "n_prims must be >= 1");
+  if (n < 0 || n > (int64_t)INT32_MAX) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(prims, "prims")) || (rc = check_ptr(points, "points")) || (rc = check_ptr(sdf, "sdf")))
+    return rc;
+  g_err[0] = 0;
+  scene_sdf_kernel<<<(unsigned)((n + 255) / 256), 256, 256 * 16 * sizeof(float), (hipStream_t)stream>>>(
+      prims, n_prims, points, n, sdf);
+  return hip_status(hipGetLastError(), "ddf_scene_sdf launch");
 }
 
 }  // extern "C"

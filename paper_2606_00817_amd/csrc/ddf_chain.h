@@ -39,6 +39,9 @@ struct Chain {
   static constexpr int RT = M / 32;                  // 32-ray tiles per workgroup
   static constexpr int NT = WIDTH / 32 / kWaves;     // 32-neuron tiles per wave
   static constexpr int LDX = WIDTH + 16 / (int)sizeof(E);  // padded LDS row (elements)
+  // LDS tile size in elements: M rows of LDX plus one more A block, so the read of the block
+  // after the last one (prefetched, never used) stays inside the allocation
+  static constexpr int XSIZE = M * LDX + 16;
 
   static __device__ inline BFrag load_b(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
     return __builtin_bit_cast(BFrag, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
@@ -61,49 +64,65 @@ struct Chain {
     const int tstride = KB * 1024;
     const E* xrow = X + (lane & 31) * LDX + (P::KBLK / 2) * (lane >> 5);
     BFrag b0[NT], b1[NT], b2[NT], b3[NT];
+    AFrag a0[RT], a1[RT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       b0[t] = load_b(rs, voff, base + t * tstride);
       b1[t] = load_b(rs, voff, base + t * tstride + 1024);
       b2[t] = load_b(rs, voff, base + t * tstride + 2048);
     }
+    load_a(a0, xrow, 0);
 #pragma unroll (KBC > 0 ? KBC / 4 : 1)
     for (int k = 0; k < KB; k += 4) {
       const int kb = base + k * 1024;
+      // each quarter: issue the weight loads three blocks ahead and the LDS read of the next
+      // block's activations, then the matrix products of this block
 #pragma unroll
       for (int t = 0; t < NT; ++t) b3[t] = load_b(rs, voff, kb + t * tstride + 3 * 1024);
+      load_a(a1, xrow, k + 1);
       __builtin_amdgcn_sched_barrier(0);
-      step(acc, xrow, k, b0);
+      mma_all(acc, a0, b0);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) b0[t] = load_b(rs, voff, kb + t * tstride + 4 * 1024);
+      load_a(a0, xrow, k + 2);
       __builtin_amdgcn_sched_barrier(0);
-      step(acc, xrow, k + 1, b1);
+      mma_all(acc, a1, b1);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) b1[t] = load_b(rs, voff, kb + t * tstride + 5 * 1024);
+      load_a(a1, xrow, k + 3);
       __builtin_amdgcn_sched_barrier(0);
-      step(acc, xrow, k + 2, b2);
+      mma_all(acc, a0, b2);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) b2[t] = load_b(rs, voff, kb + t * tstride + 6 * 1024);
+      load_a(a0, xrow, k + 4);   // one block past the end on the last pass: inside the row padding
       __builtin_amdgcn_sched_barrier(0);
-      step(acc, xrow, k + 3, b3);
+      mma_all(acc, a1, b3);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
 
-  static __device__ inline void step(f32x16 (&acc)[RT][NT], const E* xrow, int k, const BFrag (&b)[NT]) {
-    AFrag av[RT];
+  static __device__ inline void load_a(AFrag (&av)[RT], const E* xrow, int k) {
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
       av[rt] = *reinterpret_cast<const AFrag*>(xrow + rt * 32 * LDX + k * P::KBLK);
+  }
+
+  static __device__ inline void mma_all(f32x16 (&acc)[RT][NT], const AFrag (&av)[RT], const BFrag (&b)[NT]) {
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int t = 0; t < NT; ++t) P::mma(acc[rt][t], av[rt], b[t]);
   }
 };
+
+// Four consecutive elements of the operand type as one vector access.
+template <class E> struct V4T;
+template <> struct V4T<float> { using type = f32x4; };
+template <> struct V4T<__bf16> { using type = bf16x4; };
+template <class E> using V4 = typename V4T<E>::type;
 
 // Row of the 32x32 accumulator held in register v by `lane`.
 __device__ inline int acc_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }

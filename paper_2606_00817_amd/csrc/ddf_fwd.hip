@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
   using C = Chain<P, WIDTH>;
   using E = typename P::E;
   constexpr int M = C::M, RT = C::RT, NT = C::NT, LDX = C::LDX;
-  __shared__ __attribute__((aligned(16))) E X[M * LDX];
+  __shared__ __attribute__((aligned(16))) E X[C::XSIZE];
   __shared__ float headp[kWaves][M][2];
 
   const int lane = threadIdx.x & 63;
@@ -95,17 +95,17 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
             if (lane == 0) atomicMax(a.amax + l, __float_as_uint(m));
           }
         }
-        if (slab) {
+        if (MODE == kModeTrain) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int64_t g0 = ray0 + rt * 32 + 8 * q;   // 8-ray block of registers 4q..4q+3
-            E* dst = slab + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5);
-            dst[0] = (E)acc[rt][t][4 * q + 0];
-            dst[1] = (E)acc[rt][t][4 * q + 1];
-            dst[2] = (E)acc[rt][t][4 * q + 2];
-            dst[3] = (E)acc[rt][t][4 * q + 3];
+            V4<E> hv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) hv[i] = (E)acc[rt][t][4 * q + i];
+            *reinterpret_cast<V4<E>*>(slab + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5)) = hv;
           }
         }
+        __builtin_amdgcn_sched_barrier(0);   // keep the epilogue tile by tile (no hoisting)
       }
       if (last) {
 #pragma unroll

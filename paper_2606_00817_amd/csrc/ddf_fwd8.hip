@@ -79,24 +79,28 @@ __device__ inline void gemm_f8(f32x16 (&acc)[kRT8][NTP], const uint8_t* X, const
   const int base = tile0 * KB * 2048;
   const uint8_t* xrow = X + (lane & 31) * LDX + 32 * (lane >> 5);
   i32x8 b[3][NTP];
+  i32x8 av[2][kRT8];
 #pragma unroll
-  for (int s = 0; s < 2; ++s)
+  for (int st = 0; st < 2; ++st)
 #pragma unroll
-    for (int t = 0; t < NTP; ++t) b[s][t] = buf_b8(rs, voff, base + (t * KB + s) * 2048);
+    for (int t = 0; t < NTP; ++t) b[st][t] = buf_b8(rs, voff, base + (t * KB + st) * 2048);
+#pragma unroll
+  for (int rt = 0; rt < kRT8; ++rt) av[0][rt] = lds_a8(xrow + rt * 32 * LDX);
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
 #pragma unroll
     for (int t = 0; t < NTP; ++t) b[(k + 2) % 3][t] = buf_b8(rs, voff, base + (t * KB + k + 2) * 2048);
-    __builtin_amdgcn_sched_barrier(0);
-    i32x8 av[kRT8];
+    if (k + 1 < KB) {
 #pragma unroll
-    for (int rt = 0; rt < kRT8; ++rt) av[rt] = lds_a8(xrow + rt * 32 * LDX + k * 64);
+      for (int rt = 0; rt < kRT8; ++rt) av[(k + 1) & 1][rt] = lds_a8(xrow + rt * 32 * LDX + (k + 1) * 64);
+    }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int rt = 0; rt < kRT8; ++rt)
 #pragma unroll
       for (int t = 0; t < NTP; ++t)
-        acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[rt], b[k % 3][t], acc[rt][t], 0, 0, 0,
-                                                                     127, 0, 127);
+        acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[k & 1][rt], b[k % 3][t], acc[rt][t], 0, 0,
+                                                                     0, 127, 0, 127);
     __builtin_amdgcn_sched_barrier(0);
   }
 }

@@ -16,6 +16,7 @@
 namespace ddf {
 
 constexpr int kLossBlocks = 256;
+constexpr int kHeadChunks = 64;   // ray chunks of the head-gradient reduction
 
 struct TrainWs {
   int64_t R;                // padded rows
@@ -23,6 +24,7 @@ struct TrainWs {
   int64_t zt, zx, dzt, dzx; // fp32 [R]
   int64_t lossp;            // [kLossBlocks][8] floats
   int64_t scal;             // 64 bytes of scalars
+  int64_t headp;            // head-gradient partials [kHeadChunks][2][width + 2]
   int64_t grad;             // fp32 [P] (used when the caller passes no gradient buffer)
   int64_t total;
   int esize;
@@ -42,6 +44,7 @@ inline TrainWs train_ws(const ddf_net_desc& d, int64_t batch, size_t nparams) {
   w.dzx = off; off = align256(off + 4 * w.R);
   w.lossp = off; off = align256(off + 32ll * kLossBlocks);
   w.scal = off; off = align256(off + 64);
+  w.headp = off; off = align256(off + 4ll * kHeadChunks * 2 * (d.width + 2));
   w.grad = off; off = align256(off + 4 * (int64_t)nparams);
   w.total = off;
   return w;
@@ -155,6 +158,44 @@ __global__ void loss_grad_kernel(LossArgs a) {
   a.dzx[i] = gx;
 }
 
+// SDF fitting: per-block compensated sums of |s - s_gt| (slot 0 of the partials).
+__global__ void sdf_loss_partial_kernel(LossArgs a) {
+  float l1 = 0.f, l1c = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n;
+       i += (int64_t)kLossBlocks * blockDim.x)
+    kahan_add(l1, l1c, fabsf(a.zt[i] - a.tgt[i]));
+  __shared__ float red[kThreads][2];
+  red[threadIdx.x][0] = l1; red[threadIdx.x][1] = l1c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s0 = 0.f, c0 = 0.f;
+    for (int t = 0; t < kThreads; ++t) { kahan_add(s0, c0, red[t][0]); c0 += red[t][1]; }
+    float* p = a.partial + blockIdx.x * 8;
+    p[0] = s0; p[1] = c0; p[2] = 0.f; p[3] = 0.f; p[4] = 0.f;
+  }
+}
+
+__global__ void sdf_loss_final_kernel(LossArgs a) {
+  if (threadIdx.x != 0) return;
+  float s0 = 0.f, c0 = 0.f;
+  for (int b = 0; b < kLossBlocks; ++b) { kahan_add(s0, c0, a.partial[b * 8]); c0 += a.partial[b * 8 + 1]; }
+  const float l = a.n > 0 ? (s0 + c0) / (float)a.n : 0.f;
+  a.loss_out[0] = l; a.loss_out[1] = l; a.loss_out[2] = 0.f;
+}
+
+// d|s - s_gt| / ds / n (sign of 0 is 0; a NaN error stays NaN); rows n..R-1 get zeros.
+__global__ void sdf_loss_grad_kernel(LossArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.R) return;
+  float g = 0.f;
+  if (i < a.n) {
+    const float u = a.zt[i] - a.tgt[i];
+    g = u != u ? u : (u > 0.f ? 1.f : (u < 0.f ? -1.f : 0.f)) / (float)a.n;
+  }
+  a.dzt[i] = g;
+  a.dzx[i] = 0.f;
+}
+
 __global__ void copy_grads_kernel(const float* gzt, const float* gzx, float* dzt, float* dzx, int64_t n, int64_t R) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R) return;
@@ -183,7 +224,7 @@ __global__ __launch_bounds__(kThreads, 1) void bwd_chain_kernel(BwdArgs a) {
   using C = Chain<P, WIDTH>;
   using E = typename P::E;
   constexpr int M = C::M, RT = C::RT, NT = C::NT, LDX = C::LDX;
-  __shared__ __attribute__((aligned(16))) E X[M * LDX];
+  __shared__ __attribute__((aligned(16))) E X[C::XSIZE];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ray0 = (int64_t)blockIdx.x * M;
@@ -222,23 +263,33 @@ __global__ __launch_bounds__(kThreads, 1) void bwd_chain_kernel(BwdArgs a) {
     const E* Hm = H + (int64_t)(l - 1) * slab;        // H_(l-1): output of hidden layer l - 1
     E* Dm = delta + (int64_t)(l - 1) * slab;
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+    for (int t = 0; t < NT; ++t) {
+      const int n = (nt0 + t) * 32 + (lane & 31);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int n = (nt0 + t) * 32 + (lane & 31);
+      for (int rt = 0; rt < RT; ++rt) {
+        // 4 consecutive rays per register group are contiguous in the store: one vector each
+        V4<E> hm[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int64_t g0 = ray0 + rt * 32 + 8 * q;
-          const int64_t gi = ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5);
+          hm[q] = *reinterpret_cast<const V4<E>*>(Hm + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5));
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t g0 = ray0 + rt * 32 + 8 * q;
+          V4<E> dv;
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int v = 4 * q + i;
-            const float d = (float)Hm[gi + i] > 0.f ? acc[rt][t][v] : 0.f;
-            X[(rt * 32 + acc_row(v, lane)) * LDX + n] = (E)d;
-            Dm[gi + i] = (E)d;
+            const float d = (float)hm[q][i] > 0.f ? acc[rt][t][v] : 0.f;
+            dv[i] = (E)d;
+            X[(rt * 32 + acc_row(v, lane)) * LDX + n] = dv[i];
           }
+          *reinterpret_cast<V4<E>*>(Dm + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5)) = dv;
         }
       }
+      __builtin_amdgcn_sched_barrier(0);
+    }
     __syncthreads();
   }
 }
@@ -312,39 +363,49 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
   for (int r = 0; r < RTW; ++r) rsum[r] = 0.f;
   const bool do_bias = (tn == 0) && ((wave & 1) == 0);
 
+  // Loads run three steps ahead in a ring of four (steps is a multiple of 4: R is a multiple
+  // of 128); the loads past the end are bounds-checked by the buffer resources.
   const int steps = (int)(a.R / KB);
-  Frag A0[RTW], B0[2], A1[RTW], B1[2];
+  Frag A[4][RTW], B[4][2];
+  auto load = [&](int slot, int s) {
+    const int sa = s * a_step, sb = s * b_step;
 #pragma unroll
-  for (int r = 0; r < RTW; ++r) A0[r] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rd, ao[r], 0, 0));
+    for (int r = 0; r < RTW; ++r)
+      A[slot][r] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rd, ao[r], sa, 0));
 #pragma unroll
-  for (int c = 0; c < 2; ++c) B0[c] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rh, bo[c], 0, 0));
-  for (int s = 0; s < steps; s += 2) {
-    const int sa1 = (s + 1) * a_step, sb1 = (s + 1) * b_step;
-#pragma unroll
-    for (int r = 0; r < RTW; ++r) A1[r] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rd, ao[r], sa1, 0));
-#pragma unroll
-    for (int c = 0; c < 2; ++c) B1[c] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rh, bo[c], sb1, 0));
-#pragma unroll
-    for (int r = 0; r < RTW; ++r) {
-      P::mma(acc[r][0], A0[r], B0[0]);
-      P::mma(acc[r][1], A0[r], B0[1]);
-      if (do_bias)
-#pragma unroll
-        for (int j = 0; j < KB / 2; ++j) rsum[r] += (float)A0[r][j];
-    }
-    const int sa2 = (s + 2) * a_step, sb2 = (s + 2) * b_step;
-#pragma unroll
-    for (int r = 0; r < RTW; ++r) A0[r] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rd, ao[r], sa2, 0));
-#pragma unroll
-    for (int c = 0; c < 2; ++c) B0[c] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rh, bo[c], sb2, 0));
+    for (int c = 0; c < 2; ++c)
+      B[slot][c] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rh, bo[c], sb, 0));
+  };
+  auto compute = [&](int slot) {
 #pragma unroll
     for (int r = 0; r < RTW; ++r) {
-      P::mma(acc[r][0], A1[r], B1[0]);
-      P::mma(acc[r][1], A1[r], B1[1]);
+      P::mma(acc[r][0], A[slot][r], B[slot][0]);
+      P::mma(acc[r][1], A[slot][r], B[slot][1]);
       if (do_bias)
 #pragma unroll
-        for (int j = 0; j < KB / 2; ++j) rsum[r] += (float)A1[r][j];
+        for (int j = 0; j < KB / 2; ++j) rsum[r] += (float)A[slot][r][j];
     }
+  };
+  load(0, 0);
+  load(1, 1);
+  load(2, 2);
+  for (int s = 0; s < steps; s += 4) {
+    load(3, s + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(0);
+    __builtin_amdgcn_sched_barrier(0);
+    load(0, s + 4);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(1);
+    __builtin_amdgcn_sched_barrier(0);
+    load(1, s + 5);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(2);
+    __builtin_amdgcn_sched_barrier(0);
+    load(2, s + 6);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(3);
+    __builtin_amdgcn_sched_barrier(0);
   }
 
   const int fan_in = layer == 0 ? a.n_feat : W;
@@ -373,49 +434,76 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
 }
 
 // Head gradients: dW_head[o][j] = sum_r dz_o[r] H_n[r][j], db_head[o] = sum_r dz_o[r].
+// Phase 1: block (j-block of 32 neurons, ray chunk c) sums its chunk (8 ray groups per
+// block, compensated); phase 2 adds the chunks in order.  kHeadChunks chunks of R / 8
+// ray blocks each; the last phase-1 column of blocks (j-block == W / 32) does the biases.
+
 template <class E>
-__global__ void head_grad_kernel(const E* Hn, const float* dzt, const float* dzx, int64_t R, int W, int n_out,
-                                 float* gW, float* gb) {
+__global__ void head_grad_partial_kernel(const E* Hn, const float* dzt, const float* dzx, int64_t R, int W,
+                                         float* part /*[kHeadChunks][2][W + 2]*/) {
   __shared__ float red[8][32][2];
-  const int j = blockIdx.x * 32 + (threadIdx.x & 31);
-  const int grp = threadIdx.x >> 5;
+  const int jb = blockIdx.x, c = blockIdx.y;
+  const int grp = threadIdx.x >> 5, jl = threadIdx.x & 31;
+  const int64_t nblk = R / 8;
+  const int64_t per = (nblk + kHeadChunks - 1) / kHeadChunks;
+  const int64_t b0 = c * per, b1 = min(nblk, b0 + per);
   float s0 = 0.f, c0 = 0.f, s1 = 0.f, c1 = 0.f;
-  if (blockIdx.x * 32 < W) {
-    for (int64_t rb = grp; rb < R / 8; rb += 8) {
-      const E* h = Hn + (rb * W + j) * 8;
+  if (jb * 32 < W) {
+    const int j = jb * 32 + jl;
+    for (int64_t rb = b0 + grp; rb < b1; rb += 8) {
+      const V4<E> h0 = *reinterpret_cast<const V4<E>*>(Hn + (rb * W + j) * 8);
+      const V4<E> h1 = *reinterpret_cast<const V4<E>*>(Hn + (rb * W + j) * 8 + 4);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const float hv = (float)h[q];
+        const float hv = (float)(q < 4 ? h0[q] : h1[q - 4]);
         kahan_add(s0, c0, dzt[rb * 8 + q] * hv);
         kahan_add(s1, c1, dzx[rb * 8 + q] * hv);
       }
     }
-    red[grp][threadIdx.x & 31][0] = s0 + c0;
-    red[grp][threadIdx.x & 31][1] = s1 + c1;
-  }
-  __syncthreads();
-  if (blockIdx.x * 32 < W && grp == 0) {
-    float t0 = 0.f, t1 = 0.f;
-    for (int g = 0; g < 8; ++g) { t0 += red[g][threadIdx.x][0]; t1 += red[g][threadIdx.x][1]; }
-    gW[j] = t0;
-    if (n_out > 1) gW[W + j] = t1;
-  }
-  if (blockIdx.x == gridDim.x - 1) {      // the extra block: head biases
-    __shared__ float rb2[kThreads][2];
-    float a0 = 0.f, a0c = 0.f, a1 = 0.f, a1c = 0.f;
-    for (int64_t i = threadIdx.x; i < R; i += kThreads) {
-      kahan_add(a0, a0c, dzt[i]);
-      kahan_add(a1, a1c, dzx[i]);
+  } else {
+    for (int64_t r = b0 * 8 + threadIdx.x; r < b1 * 8; r += kThreads) {
+      kahan_add(s0, c0, dzt[r]);
+      kahan_add(s1, c1, dzx[r]);
     }
-    rb2[threadIdx.x][0] = a0 + a0c;
-    rb2[threadIdx.x][1] = a1 + a1c;
+  }
+  if (jb * 32 < W) {
+    red[grp][jl][0] = s0 + c0;
+    red[grp][jl][1] = s1 + c1;
+    __syncthreads();
+    if (grp == 0) {
+      float t0 = 0.f, t1 = 0.f;
+      for (int g = 0; g < 8; ++g) { t0 += red[g][jl][0]; t1 += red[g][jl][1]; }
+      part[((int64_t)c * 2 + 0) * (W + 2) + jb * 32 + jl] = t0;
+      part[((int64_t)c * 2 + 1) * (W + 2) + jb * 32 + jl] = t1;
+    }
+  } else {
+    __shared__ float rb2[kThreads][2];
+    rb2[threadIdx.x][0] = s0 + c0;
+    rb2[threadIdx.x][1] = s1 + c1;
     __syncthreads();
     if (threadIdx.x == 0) {
-      float t0 = 0.f, t1 = 0.f, u0 = 0.f, u1 = 0.f;
-      for (int t = 0; t < kThreads; ++t) { kahan_add(t0, u0, rb2[t][0]); kahan_add(t1, u1, rb2[t][1]); }
-      gb[0] = t0 + u0;
-      if (n_out > 1) gb[1] = t1 + u1;
+      float t0 = 0.f, t1 = 0.f;
+      for (int t = 0; t < kThreads; ++t) { t0 += rb2[t][0]; t1 += rb2[t][1]; }
+      part[((int64_t)c * 2 + 0) * (W + 2) + W] = t0;
+      part[((int64_t)c * 2 + 1) * (W + 2) + W] = t1;
     }
+  }
+}
+
+__global__ void head_grad_final_kernel(const float* part, int W, int n_out, float* gW, float* gb) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > W) return;
+  float t0 = 0.f, c0 = 0.f, t1 = 0.f, c1 = 0.f;
+  for (int c = 0; c < kHeadChunks; ++c) {
+    kahan_add(t0, c0, part[((int64_t)c * 2 + 0) * (W + 2) + j]);
+    kahan_add(t1, c1, part[((int64_t)c * 2 + 1) * (W + 2) + j]);
+  }
+  if (j < W) {
+    gW[j] = t0 + c0;
+    if (n_out > 1) gW[W + j] = t1 + c1;
+  } else {
+    gb[0] = t0 + c0;
+    if (n_out > 1) gb[1] = t1 + c1;
   }
 }
 
@@ -459,6 +547,30 @@ static int check_rows(const ddf_net_desc& d, const TrainWs& w) {
   if ((int64_t)d.width * w.R * w.esize >= (1ll << 31))
     return fail(DDF_ERR_UNSUPPORTED, "batch too large: one activation slab must stay below 2 GiB");
   return DDF_OK;
+}
+
+static int check_hp(const ddf_train_hparams* hp) {
+  if (!hp) return fail(DDF_ERR_INVALID_ARG, "hp is NULL");
+  if (hp->step < 1) return fail(DDF_ERR_INVALID_ARG, "step must be >= 1");
+  if (!(hp->lr >= 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) ||
+      !(hp->eps > 0.f))
+    return fail(DDF_ERR_INVALID_ARG, "hyper-parameters out of range");
+  return DDF_OK;
+}
+
+// Adam on the fp32 master (skipped as a whole when any gradient is not finite), then the
+// repack of the working copy.
+static int run_adam(const ddf_net_desc& d, float* master, float* adam_m, float* adam_v, void* packed,
+                    const float* grad, size_t P, const ddf_train_hparams* hp, int32_t* flag, hipStream_t st) {
+  int rc;
+  zero_flag_kernel<<<1, 64, 0, st>>>(flag);
+  finite_check_kernel<<<1024, 256, 0, st>>>(grad, (int64_t)P, flag);
+  const double bc1 = 1.0 - pow((double)hp->beta1, (double)hp->step);
+  const double bc2 = 1.0 - pow((double)hp->beta2, (double)hp->step);
+  adam_kernel<<<2048, 256, 0, st>>>(master, adam_m, adam_v, grad, (int64_t)P, flag, hp->lr, hp->beta1,
+                                    hp->beta2, hp->eps, (float)bc1, (float)bc2);
+  if ((rc = hip_status(hipGetLastError(), "adam launch"))) return rc;
+  return hip_status(launch_pack(d, master, nullptr, packed, st, true), "repack launch");
 }
 
 static size_t param_count_of(const ddf_net_desc& d) {
@@ -513,16 +625,17 @@ static int run_backward(const ddf_net_desc& d, const void* packed, const TrainWs
   e = d.precision == DDF_FP32 ? launch_dw<PF32>(d, a, st) : launch_dw<PBF16>(d, a, st);
   if (e != hipSuccess) return hip_status(e, "weight-gradient launch");
   const int64_t hslab = ((int64_t)L.k1_half + (int64_t)(d.n_hidden - 1) * d.width) * w.R * w.esize;
-  const unsigned hb = (unsigned)(d.width / 32 + 1);
+  const dim3 hb((unsigned)(d.width / 32 + 1), kHeadChunks);
   const MasterOffsets mo = master_offsets(d);
+  float* part = reinterpret_cast<float*>(ws + w.headp);
   if (d.precision == DDF_FP32)
-    head_grad_kernel<float><<<hb, kThreads, 0, st>>>(reinterpret_cast<const float*>(ws + w.act + hslab),
-                                                     b.dzt, b.dzx, w.R, d.width, d.n_out, grad + mo.w[d.n_hidden],
-                                                     grad + mo.b[d.n_hidden]);
+    head_grad_partial_kernel<float><<<hb, kThreads, 0, st>>>(reinterpret_cast<const float*>(ws + w.act + hslab),
+                                                             b.dzt, b.dzx, w.R, d.width, part);
   else
-    head_grad_kernel<__bf16><<<hb, kThreads, 0, st>>>(reinterpret_cast<const __bf16*>(ws + w.act + hslab),
-                                                      b.dzt, b.dzx, w.R, d.width, d.n_out, grad + mo.w[d.n_hidden],
-                                                      grad + mo.b[d.n_hidden]);
+    head_grad_partial_kernel<__bf16><<<hb, kThreads, 0, st>>>(reinterpret_cast<const __bf16*>(ws + w.act + hslab),
+                                                              b.dzt, b.dzx, w.R, d.width, part);
+  head_grad_final_kernel<<<(unsigned)(d.width / 256 + 1), 256, 0, st>>>(part, d.width, d.n_out, grad + mo.w[d.n_hidden],
+                                                                       grad + mo.b[d.n_hidden]);
   return hip_status(hipGetLastError(), "head-gradient launch");
 }
 
@@ -596,12 +709,10 @@ int ddf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
   int rc;
   if ((rc = check_train_desc(d))) return rc;
   if (d->n_in != 6 || d->n_out != 2) return fail(DDF_ERR_INVALID_ARG, "ddf_train_step needs a DDF net (n_in 6, n_out 2)");
-  if (!hp) return fail(DDF_ERR_INVALID_ARG, "hp is NULL");
+  if ((rc = check_hp(hp))) return rc;
+  if (!(hp->l1_clamp > 0.f) || !(hp->bce_weight >= 0.f))
+    return fail(DDF_ERR_INVALID_ARG, "loss hyper-parameters out of range");
   if (batch < 1 || batch > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "batch = %lld out of range", (long long)batch);
-  if (hp->step < 1) return fail(DDF_ERR_INVALID_ARG, "step must be >= 1");
-  if (!(hp->lr >= 0.f) || !(hp->beta1 >= 0.f && hp->beta1 < 1.f) || !(hp->beta2 >= 0.f && hp->beta2 < 1.f) ||
-      !(hp->eps > 0.f) || !(hp->l1_clamp > 0.f) || !(hp->bce_weight >= 0.f))
-    return fail(DDF_ERR_INVALID_ARG, "hyper-parameters out of range");
   if ((rc = check_ptr(master, "master")) || (rc = check_ptr(adam_m, "adam_m")) || (rc = check_ptr(adam_v, "adam_v")) ||
       (rc = check_ptr(packed, "packed")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(t_gt, "t_gt")) ||
       (rc = check_ptr(hit_gt, "hit_gt")) || (rc = check_ptr(loss_out, "loss_out")) ||
@@ -632,14 +743,46 @@ int ddf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
   if ((rc = hip_status(hipGetLastError(), "loss launch"))) return rc;
   float* grad = grad_out ? grad_out : reinterpret_cast<float*>(wb + w.grad);
   if ((rc = run_backward(*d, packed, w, wb, grad, st))) return rc;
-  zero_flag_kernel<<<1, 64, 0, st>>>(nonfinite_flag);
-  finite_check_kernel<<<1024, 256, 0, st>>>(grad, (int64_t)P, nonfinite_flag);
-  const double bc1 = 1.0 - pow((double)hp->beta1, (double)hp->step);
-  const double bc2 = 1.0 - pow((double)hp->beta2, (double)hp->step);
-  adam_kernel<<<2048, 256, 0, st>>>(master, adam_m, adam_v, grad, (int64_t)P, nonfinite_flag, hp->lr, hp->beta1,
-                                    hp->beta2, hp->eps, (float)bc1, (float)bc2);
-  if ((rc = hip_status(hipGetLastError(), "adam launch"))) return rc;
-  return hip_status(launch_pack(*d, master, nullptr, packed, st, true), "repack launch");
+  return run_adam(*d, master, adam_m, adam_v, packed, grad, P, hp, nonfinite_flag, st);
+}
+
+int sdf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* adam_v, void* packed,
+                   const float* points, const float* sdf_gt, int64_t n, const ddf_train_hparams* hp,
+                   float* loss_out, int32_t* nonfinite_flag, float* grad_out, void* ws, size_t ws_bytes,
+                   void* stream) {
+  int rc;
+  if ((rc = check_train_desc(d))) return rc;
+  if (d->n_in != 3 || d->n_out != 1) return fail(DDF_ERR_INVALID_ARG, "sdf_train_step needs an SDF net (n_in 3, n_out 1)");
+  if ((rc = check_hp(hp))) return rc;
+  if (n < 1 || n > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if ((rc = check_ptr(master, "master")) || (rc = check_ptr(adam_m, "adam_m")) || (rc = check_ptr(adam_v, "adam_v")) ||
+      (rc = check_ptr(packed, "packed")) || (rc = check_ptr(points, "points")) || (rc = check_ptr(sdf_gt, "sdf_gt")) ||
+      (rc = check_ptr(loss_out, "loss_out")) || (rc = check_ptr(nonfinite_flag, "nonfinite_flag")) ||
+      (rc = check_ptr(ws, "ws")))
+    return rc;
+  if (grad_out && (rc = check_ptr(grad_out, "grad_out"))) return rc;
+  const size_t P = param_count_of(*d);
+  const TrainWs w = train_ws(*d, n, P);
+  if ((rc = check_rows(*d, w))) return rc;
+  if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* wb = static_cast<uint8_t*>(ws);
+  float* zt = reinterpret_cast<float*>(wb + w.zt);
+  g_err_clear();
+  if ((rc = run_forward_train(*d, packed, points, n, zt, zt, w, wb, st))) return rc;
+  LossArgs la{};
+  la.zt = zt; la.tgt = sdf_gt; la.n = n; la.R = w.R;
+  la.partial = reinterpret_cast<float*>(wb + w.lossp);
+  la.loss_out = loss_out;
+  la.dzt = reinterpret_cast<float*>(wb + w.dzt);
+  la.dzx = reinterpret_cast<float*>(wb + w.dzx);
+  sdf_loss_partial_kernel<<<kLossBlocks, kThreads, 0, st>>>(la);
+  sdf_loss_final_kernel<<<1, 64, 0, st>>>(la);
+  sdf_loss_grad_kernel<<<(unsigned)((w.R + 255) / 256), 256, 0, st>>>(la);
+  if ((rc = hip_status(hipGetLastError(), "sdf loss launch"))) return rc;
+  float* grad = grad_out ? grad_out : reinterpret_cast<float*>(wb + w.grad);
+  if ((rc = run_backward(*d, packed, w, wb, grad, st))) return rc;
+  return run_adam(*d, master, adam_m, adam_v, packed, grad, P, hp, nonfinite_flag, st);
 }
 
 }  // extern "C"

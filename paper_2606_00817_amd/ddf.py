@@ -60,6 +60,9 @@ SIGNATURES = {
                                         _P, _P, _P, _P, _SZ, _P]),
     "sdf_eval": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P]),
     "ddf_cast_targets": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P, _P, _P]),
+    "ddf_scene_sdf": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P, _P]),
+    "sdf_train_step": (ctypes.c_int, [_D, _P, _P, _P, _P, _P, _P, _I64, ctypes.POINTER(TrainHParamsC),
+                                      _P, _P, _P, _P, _SZ, _P]),
 }
 
 
@@ -183,6 +186,7 @@ def scene_prims(scene) -> np.ndarray:
     out[:, 0:3] = scene.centers
     out[:, 3:6] = 1.0 / np.asarray(scene.axes)
     out[:, 6:15] = np.transpose(np.asarray(scene.rot), (0, 2, 1)).reshape(P, 9)
+    out[:, 15] = np.asarray(scene.axes).min(axis=1)
     return out
 
 
@@ -195,6 +199,28 @@ def cast_targets(prims: torch.Tensor, rays: torch.Tensor):
     hit = torch.empty(n, dtype=torch.uint8, device=rays.device)
     _check(lib().ddf_cast_targets(_ptr(prims), prims.shape[0], _ptr(rays), n, _ptr(t), _ptr(hit), _stream()))
     return t, hit
+
+
+def scene_sdf(prims: torch.Tensor, points: torch.Tensor):
+    """Signed-distance bound of the analytic union at float32 SoA points [3, n]."""
+    _dev(prims, torch.float32, "prims")
+    _dev(points, torch.float32, "points")
+    n = points.shape[1]
+    s = torch.empty(n, dtype=torch.float32, device=points.device)
+    _check(lib().ddf_scene_sdf(_ptr(prims), prims.shape[0], _ptr(points), n, _ptr(s), _stream()))
+    return s
+
+
+def sdf_train_step(desc, precision, master, m, v, packed, points, sdf_gt, hp: TrainHParamsC, ws,
+                   loss_out=None, flag=None, grad_out=None):
+    d = desc_c(desc, precision)
+    dev = points.device
+    loss_out = loss_out if loss_out is not None else torch.empty(4, dtype=torch.float32, device=dev)
+    flag = flag if flag is not None else torch.empty(4, dtype=torch.int32, device=dev)
+    _check(lib().sdf_train_step(ctypes.byref(d), _ptr(master), _ptr(m), _ptr(v), _ptr(packed), _ptr(points),
+                                _ptr(sdf_gt), points.shape[1], ctypes.byref(hp), _ptr(loss_out), _ptr(flag),
+                                _ptr(grad_out), _ptr(ws), ws.numel(), _stream()))
+    return loss_out, flag
 
 
 def train_workspace_bytes(desc, precision, batch) -> int:

@@ -301,6 +301,17 @@ def mixed_rays(scene: Scene, n: int, seed: int) -> np.ndarray:
     return np.ascontiguousarray(allr[:, perm])
 
 
+def sdf_train_points(scene: Scene, n: int, seed: int, sigma: float = 0.05) -> np.ndarray:
+    """SDF fitting samples, float32 [3, N]: half uniform in the box, half surface points
+    displaced by isotropic N(0, sigma^2) noise."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = n // 2
+    u = rng.uniform(-BOX_HALF, BOX_HALF, (h, 3))
+    p, _ = surface_points(scene, n - h, seed + 1)
+    p = p + rng.standard_normal(p.shape) * sigma
+    return np.ascontiguousarray(np.concatenate([u, p]).T.astype(np.float32))
+
+
 def sdf_points(n: int, seed: int) -> np.ndarray:
     """Points uniform in the object box as float32 [3, N] (SDF fitting inputs)."""
     rng = np.random.Generator(np.random.PCG64(seed))

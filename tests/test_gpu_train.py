@@ -198,3 +198,61 @@ def test_nonfinite_gradient_skips_update():
     assert int(flag.cpu()[0]) == 1
     for a, b in zip(before, (master, m, v)):
         assert torch.equal(a, b)
+
+
+def test_fp32_training_trajectory_matches_oracle():
+    """Four fp32 Adam steps on the 12 x 1024 net follow the oracle's own trajectory
+    (including the loss spike that Adam's early sign-like steps cause at lr 1e-3)."""
+    dev = cuda()
+    desc = I.NET_FULL
+    n = 384
+    rays, tg, hit = _train_inputs(desc, n, 1006)
+    p0 = I.he_init(desc, 0)
+    p = p0.astype(np.float64); m = np.zeros_like(p); v = np.zeros_like(p)
+    ref = []
+    for s in range(1, 5):
+        (tot, _, _), g = O.ddf_loss_and_grad(desc, p.astype(np.float32), rays, tg, hit)
+        ref.append(tot)
+        p, m, v = O.adam_step(p, m, v, g, s, 1e-3)
+        p = p.astype(np.float32).astype(np.float64)     # the master is float32
+    master = _t(p0, dev); mm = torch.zeros_like(master); vv = torch.zeros_like(master)
+    packed = ddf.pack(desc, "fp32", master)
+    ws = _ws(desc, "fp32", n, dev)
+    got = []
+    for s in range(1, 5):
+        loss, flag = ddf.train_step(desc, "fp32", master, mm, vv, packed, _t(rays, dev), _t(tg, dev),
+                                    _t(hit, dev), _hp(s, 1e-3), ws)
+        got.append(float(loss[0].item()))
+    print("fp32 trajectory", got, "oracle", ref)
+    np.testing.assert_allclose(got, ref, rtol=1e-2)
+    np.testing.assert_allclose(got[:2], ref[:2], rtol=1e-5)
+
+
+def test_scene_sdf_matches_oracle():
+    dev = cuda()
+    sc = I.scene_mixed(256, 2)
+    pts = I.sdf_train_points(sc, 4096 + 13, 31)
+    got = ddf.scene_sdf(_t(ddf.scene_prims(sc), dev), _t(pts, dev)).cpu().numpy()
+    ref = G.sdf(sc, pts.T.astype(np.float64))
+    np.testing.assert_allclose(got, ref, atol=2e-6, rtol=2e-5)
+
+
+def test_sdf_train_step_matches_oracle():
+    dev = cuda()
+    desc = I.NetDesc(3, 10, 3, 256, 1)
+    params = I.test_params(desc, 15)
+    sc = I.scene_mixed(256, 2)
+    pts = I.sdf_train_points(sc, 1000, 32)
+    gt = G.sdf(sc, pts.T.astype(np.float64)).astype(np.float32)
+    master = _t(params, dev); m = torch.zeros_like(master); v = torch.zeros_like(master)
+    packed = ddf.pack(desc, "fp32", master)
+    ws = _ws(desc, "fp32", pts.shape[1], dev)
+    grad = torch.empty_like(master)
+    loss, flag = ddf.sdf_train_step(desc, "fp32", master, m, v, packed, _t(pts, dev), _t(gt, dev), _hp(1),
+                                    ws, grad_out=grad)
+    torch.cuda.synchronize()
+    ref_loss, ref_grad = O.sdf_loss_and_grad(desc, params, pts.T, gt)
+    assert int(flag.cpu()[0]) == 0
+    assert float(loss.cpu()[0]) == pytest.approx(ref_loss, rel=1e-5)
+    worst = max(e for e, _ in _per_layer_errors(desc, grad.cpu().numpy().astype(np.float64), ref_grad))
+    assert worst < 2e-4

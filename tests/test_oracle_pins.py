@@ -437,3 +437,20 @@ def test_emulated_bf16_backward_matches_brute_force():
                      for i in range(W.shape[1])]
     ref = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in acc])
     np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-14)
+
+
+def test_sdf_loss_gradient_matches_central_differences():
+    desc = I.NetDesc(3, 4, 3, 32, 1)
+    params = I.test_params(desc, 2).astype(np.float64)
+    sc = I.scene_mixed(8, 3)
+    pts = I.sdf_train_points(sc, 40, 4).T.astype(np.float64)
+    gt = G.sdf(sc, pts)
+    loss, grad = O.sdf_loss_and_grad(desc, params, pts, gt)
+    assert loss == pytest.approx(np.mean(np.abs(O.sdf_eval(desc, params, pts) - gt)), rel=1e-14)
+    rng = np.random.default_rng(1)
+    h = 1e-6
+    for k in rng.choice(len(params), 60, replace=False):
+        pp = params.copy(); pp[k] += h
+        pm = params.copy(); pm[k] -= h
+        fd = (O.sdf_loss_and_grad(desc, pp, pts, gt)[0] - O.sdf_loss_and_grad(desc, pm, pts, gt)[0]) / (2 * h)
+        assert abs(fd - grad[k]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9
