@@ -53,7 +53,11 @@ struct Chain {
   // ahead in a ring of four; KB is a multiple of 4, and the loads past the end of the
   // layer are bounds-checked by the buffer resource (they return zeros, never used).
   // KBC > 0 fixes KB at compile time (hidden layers): the k loop is then fully unrolled.
-  template <int KBC>
+  // TRANS = false: acc[rt][t] = X_tile * W_tile^T (rows rays, columns neurons).
+  // TRANS = true : acc[rt][t] = W_tile * X_tile^T (rows neurons, columns rays): the same
+  //   operand blocks with their matrix-core roles swapped, so that each lane ends up with 4
+  //   consecutive neurons of one ray per register group.
+  template <int KBC, bool TRANS = false>
   static __device__ inline void gemm(f32x16 (&acc)[RT][NT], const E* X, const void* W, int KB_rt,
                                      int nt0, int lane) {
     const int KB = KBC > 0 ? KBC : KB_rt;
@@ -81,25 +85,25 @@ struct Chain {
       for (int t = 0; t < NT; ++t) b3[t] = load_b(rs, voff, kb + t * tstride + 3 * 1024);
       load_a(a1, xrow, k + 1);
       __builtin_amdgcn_sched_barrier(0);
-      mma_all(acc, a0, b0);
+      mma_all<TRANS>(acc, a0, b0);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) b0[t] = load_b(rs, voff, kb + t * tstride + 4 * 1024);
       load_a(a0, xrow, k + 2);
       __builtin_amdgcn_sched_barrier(0);
-      mma_all(acc, a1, b1);
+      mma_all<TRANS>(acc, a1, b1);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) b1[t] = load_b(rs, voff, kb + t * tstride + 5 * 1024);
       load_a(a1, xrow, k + 3);
       __builtin_amdgcn_sched_barrier(0);
-      mma_all(acc, a0, b2);
+      mma_all<TRANS>(acc, a0, b2);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < NT; ++t) b2[t] = load_b(rs, voff, kb + t * tstride + 6 * 1024);
       load_a(a0, xrow, k + 4);   // one block past the end on the last pass: inside the row padding
       __builtin_amdgcn_sched_barrier(0);
-      mma_all(acc, a1, b3);
+      mma_all<TRANS>(acc, a1, b3);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -110,11 +114,17 @@ struct Chain {
       av[rt] = *reinterpret_cast<const AFrag*>(xrow + rt * 32 * LDX + k * P::KBLK);
   }
 
+  template <bool TRANS>
   static __device__ inline void mma_all(f32x16 (&acc)[RT][NT], const AFrag (&av)[RT], const BFrag (&b)[NT]) {
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int t = 0; t < NT; ++t) P::mma(acc[rt][t], av[rt], b[t]);
+      for (int t = 0; t < NT; ++t) {
+        if (TRANS)
+          P::mma(acc[rt][t], b[t], av[rt]);
+        else
+          P::mma(acc[rt][t], av[rt], b[t]);
+      }
   }
 };
 

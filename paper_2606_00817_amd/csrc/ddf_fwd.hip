@@ -20,6 +20,76 @@
 
 namespace ddf {
 
+// Epilogue of a layer computed with swapped operand roles (query modes): register group q of
+// tile (rt, t) holds neurons (nt0 + t) 32 + 8 q + 4 (lane / 32) + i, i < 4, of ray
+// rt 32 + lane % 32.  Bias + ReLU, then either one vector write of the 4 values into the
+// LDS tile, or (last layer) the heads' partial dot products: one value per ray and head per
+// lane, the two lane halves added, then written per wave for the fixed-order final sum.
+template <class P, int WIDTH, int MODE>
+__device__ inline void epilogue_t(const FwdArgs& a, f32x16 (&acc)[Chain<P, WIDTH>::RT][Chain<P, WIDTH>::NT],
+                                  typename P::E* X, float (*headp)[Chain<P, WIDTH>::M][2], int l, int64_t ray0,
+                                  int64_t n_act, int nt0, int lane, int wave) {
+  using C = Chain<P, WIDTH>;
+  using E = typename P::E;
+  constexpr int RT = C::RT, NT = C::NT, LDX = C::LDX;
+  const float* bias = reinterpret_cast<const float*>(a.packed + a.lay.b_off) + (int64_t)l * WIDTH;
+  const float* hw = reinterpret_cast<const float*>(a.packed + a.lay.head_w_off);
+  const bool last = (l + 1 == a.n_hidden);
+  float hp0[RT], hp1[RT], mx = 0.f;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) { hp0[rt] = 0.f; hp1[rt] = 0.f; }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int nb = (nt0 + t) * 32 + 4 * (lane >> 5);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 b4 = *reinterpret_cast<const f32x4*>(bias + nb + 8 * q);
+      f32x4 w0 = {}, w1 = {};
+      if (last) {
+        w0 = *reinterpret_cast<const f32x4*>(hw + nb + 8 * q);
+        if (a.n_out > 1) w1 = *reinterpret_cast<const f32x4*>(hw + WIDTH + nb + 8 * q);
+      }
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        f32x4 y;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) y[i] = fmaxf(acc[rt][t][4 * q + i] + b4[i], 0.f);
+        if (last) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            hp0[rt] = fmaf(w0[i], y[i], hp0[rt]);
+            hp1[rt] = fmaf(w1[i], y[i], hp1[rt]);
+          }
+        } else {
+          V4<E> yv;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) yv[i] = (E)y[i];
+          *reinterpret_cast<V4<E>*>(X + (rt * 32 + (lane & 31)) * LDX + nb + 8 * q) = yv;
+          if (MODE == kModeCalib && ray0 + rt * 32 + (lane & 31) < n_act)
+            mx = fmaxf(mx, fmaxf(fmaxf(y[0], y[1]), fmaxf(y[2], y[3])));
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (last) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const float s0 = hp0[rt] + __shfl_xor(hp0[rt], 32);   // the other 128 neurons of this tile
+      const float s1 = hp1[rt] + __shfl_xor(hp1[rt], 32);
+      if (lane < 32) {
+        headp[wave][rt * 32 + lane][0] = s0;
+        headp[wave][rt * 32 + lane][1] = s1;
+      }
+    }
+  }
+  if (MODE == kModeCalib && !last) {
+    for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (lane == 0) atomicMax(a.amax + l, __float_as_uint(mx));
+  }
+  __syncthreads();
+}
+
 template <class P, int WIDTH, int MODE>
 __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
   using C = Chain<P, WIDTH>;
@@ -52,11 +122,16 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
+    constexpr bool kTrans = MODE != kModeTrain;
     if (l == 0)
-      C::template gemm<0>(acc, X, W, K / P::KBLK, nt0, lane);
+      C::template gemm<0, kTrans>(acc, X, W, K / P::KBLK, nt0, lane);
     else
-      C::template gemm<WIDTH / P::KBLK>(acc, X, W, K / P::KBLK, nt0, lane);
+      C::template gemm<WIDTH / P::KBLK, kTrans>(acc, X, W, K / P::KBLK, nt0, lane);
     __syncthreads();   // every wave is done reading X
+    if constexpr (kTrans) {
+      epilogue_t<P, WIDTH, MODE>(a, acc, X, headp, l, ray0, n_act, nt0, lane, wave);
+      continue;
+    }
 
     const float* bias = bias_all + (int64_t)l * WIDTH;
     const bool last = (l + 1 == a.n_hidden);

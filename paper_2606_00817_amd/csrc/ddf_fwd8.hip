@@ -62,7 +62,7 @@ __device__ inline void gemm_l1(f32x16 (&acc)[kRT8][NTP], const __bf16* G, const 
     for (int rt = 0; rt < kRT8; ++rt)
 #pragma unroll
       for (int t = 0; t < NTP; ++t)
-        acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[rt], b[t], acc[rt][t], 0, 0, 0);
+        acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[t], av[rt], acc[rt][t], 0, 0, 0);
   }
 }
 
@@ -99,7 +99,7 @@ __device__ inline void gemm_f8(f32x16 (&acc)[kRT8][NTP], const uint8_t* X, const
     for (int rt = 0; rt < kRT8; ++rt)
 #pragma unroll
       for (int t = 0; t < NTP; ++t)
-        acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av[k & 1][rt], b[k % 3][t], acc[rt][t], 0, 0,
+        acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(b[k % 3][t], av[k & 1][rt], acc[rt][t], 0, 0,
                                                                      0, 127, 0, 127);
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -127,7 +127,6 @@ __global__ __launch_bounds__(kThreads, 1) void fwd8_kernel(FwdArgs a) {
   aa.n = n_act;
 
   encode_tile<__bf16, kM8, kLDG, MODE>(aa, ray0, G);
-  for (int i = threadIdx.x; i < kWaves * kM8 * 2; i += kThreads) (&headp[0][0][0])[i] = 0.f;
   __syncthreads();
 
   const float* bias_all = reinterpret_cast<const float*>(a.packed + a.lay.b_off);
@@ -141,7 +140,13 @@ __global__ __launch_bounds__(kThreads, 1) void fwd8_kernel(FwdArgs a) {
     const float qn = scales[4 * l + kQuantNext];
     const float* bias = bias_all + (int64_t)l * WIDTH;
     const void* W = a.packed + a.lay.w_off[l];
-    uint32_t hold[kRT8][NTP][4];             // pass-0 e4m3 results, 4 rows per word
+    // Operand roles are swapped (weights as the first matrix-core operand): register group q
+    // of tile (rt, t) holds neurons (tile0 + t) 32 + 8 q + 4 (lane / 32) + i, i < 4, of ray
+    // rt 32 + lane % 32, so 4 consecutive e4m3 results leave as one 32-bit LDS write.
+    uint32_t hold[kRT8][NTP][4];             // pass-0 e4m3 results, 4 neurons per word
+    float hp0[kRT8], hp1[kRT8];
+#pragma unroll
+    for (int rt = 0; rt < kRT8; ++rt) { hp0[rt] = 0.f; hp1[rt] = 0.f; }
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const int tile0 = wave * NTW + p * NTP;
@@ -157,67 +162,61 @@ __global__ __launch_bounds__(kThreads, 1) void fwd8_kernel(FwdArgs a) {
       if (p == 1) {
         __syncthreads();   // every wave is done reading this layer's input
         if (!last) {
-          // the pass-0 results go in first, then pass 1 straight from the accumulators
 #pragma unroll
           for (int rt = 0; rt < kRT8; ++rt)
 #pragma unroll
             for (int t = 0; t < NTP; ++t) {
-              const int n = (wave * NTW + t) * 32 + (lane & 31);
+              const int nb = (wave * NTW + t) * 32 + 4 * (lane >> 5);
 #pragma unroll
               for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                  X[(rt * 32 + acc_row(4 * q + i, lane)) * LDX + n] = (uint8_t)(hold[rt][t][q] >> (8 * i));
+                *reinterpret_cast<uint32_t*>(X + (rt * 32 + (lane & 31)) * LDX + nb + 8 * q) = hold[rt][t][q];
             }
         }
       }
 #pragma unroll
-      for (int rt = 0; rt < kRT8; ++rt) {
-        float hp0[16], hp1[16];
+      for (int t = 0; t < NTP; ++t) {
+        const int nb = (tile0 + t) * 32 + 4 * (lane >> 5);
 #pragma unroll
-        for (int v = 0; v < 16; ++v) { hp0[v] = 0.f; hp1[v] = 0.f; }
-#pragma unroll
-        for (int t = 0; t < NTP; ++t) {
-          const int n = (tile0 + t) * 32 + (lane & 31);
-          const float bv = bias[n];
-          float y[16];
-#pragma unroll
-          for (int v = 0; v < 16; ++v) y[v] = fmaxf(fmaf(acc[rt][t][v], dq, bv), 0.f);
+        for (int q = 0; q < 4; ++q) {
+          const f32x4 b4 = *reinterpret_cast<const f32x4*>(bias + nb + 8 * q);
+          f32x4 w0 = {}, w1 = {};
           if (last) {
-            const float w0 = hw[n];
-            const float w1 = a.n_out > 1 ? hw[WIDTH + n] : 0.f;
+            w0 = *reinterpret_cast<const f32x4*>(hw + nb + 8 * q);
+            if (a.n_out > 1) w1 = *reinterpret_cast<const f32x4*>(hw + WIDTH + nb + 8 * q);
+          }
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              hp0[v] = fmaf(w0, y[v], hp0[v]);
-              hp1[v] = fmaf(w1, y[v], hp1[v]);
-            }
-          } else if (p == 0) {
+          for (int rt = 0; rt < kRT8; ++rt) {
+            float y[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int i = 0; i < 4; ++i) y[i] = fmaxf(fmaf(acc[rt][t][4 * q + i], dq, b4[i]), 0.f);
+            if (last) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                hp0[rt] = fmaf(w0[i], y[i], hp0[rt]);
+                hp1[rt] = fmaf(w1[i], y[i], hp1[rt]);
+              }
+            } else {
               uint32_t w = 0;
 #pragma unroll
-              for (int i = 0; i < 4; ++i) w |= (uint32_t)to_e4m3(y[4 * q + i] * qn) << (8 * i);
-              hold[rt][t][q] = w;
+              for (int i = 0; i < 4; ++i) w |= (uint32_t)to_e4m3(y[i] * qn) << (8 * i);
+              if (p == 0)
+                hold[rt][t][q] = w;
+              else
+                *reinterpret_cast<uint32_t*>(X + (rt * 32 + (lane & 31)) * LDX + nb + 8 * q) = w;
             }
-          } else {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) X[(rt * 32 + acc_row(v, lane)) * LDX + n] = to_e4m3(y[v] * qn);
           }
         }
-        if (last) {
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if (last) {
 #pragma unroll
-          for (int v = 0; v < 16; ++v) {
-            hp0[v] = wave_sum32(hp0[v]);
-            hp1[v] = wave_sum32(hp1[v]);
-          }
-          if ((lane & 31) == 0) {
-#pragma unroll
-            for (int v = 0; v < 16; ++v) {
-              const int r = rt * 32 + acc_row(v, lane);
-              headp[wave][r][0] += hp0[v];   // pass 0 then pass 1, same lane: fixed order
-              headp[wave][r][1] += hp1[v];
-            }
-          }
+      for (int rt = 0; rt < kRT8; ++rt) {
+        const float s0 = hp0[rt] + __shfl_xor(hp0[rt], 32);
+        const float s1 = hp1[rt] + __shfl_xor(hp1[rt], 32);
+        if (lane < 32) {
+          headp[wave][rt * 32 + lane][0] = s0;
+          headp[wave][rt * 32 + lane][1] = s1;
         }
       }
     }
