@@ -94,7 +94,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--legs", default="precisions,train,trace,cpu",
-                    help="comma list of extra legs: precisions, train, trace, cpu")
+                    help="comma list of extra legs: precisions, train, trace, cpu, copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
@@ -134,6 +134,15 @@ def main():
         ms = timer.time(lambda: ddf.query_into(dc, packed, rays, t, xi), steps)
         torch.cuda.synchronize()
         return ms, t.cpu().numpy(), xi.cpu().numpy()
+
+    if "copy" in legs:
+        # a plain copy kernel of known size (1 GiB read + 1 GiB written): the reference that
+        # scales the memory counters of a profiled run
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- the timed region: K steps of the headline-precision query
     prec = args.precision

@@ -30,14 +30,14 @@ struct PBF16 {
   }
 };
 
-template <class P, int WIDTH>
+template <class P, int WIDTH, int WAVES = kWaves>
 struct Chain {
   using E = typename P::E;
   using AFrag = typename P::AFrag;
   using BFrag = typename P::BFrag;
   static constexpr int M = P::M;
   static constexpr int RT = M / 32;                  // 32-ray tiles per workgroup
-  static constexpr int NT = WIDTH / 32 / kWaves;     // 32-neuron tiles per wave
+  static constexpr int NT = WIDTH / 32 / WAVES;      // 32-neuron tiles per wave
   static constexpr int LDX = WIDTH + 16 / (int)sizeof(E);  // padded LDS row (elements)
   // LDS tile size in elements: M rows of LDX plus one more A block, so the read of the block
   // after the last one (prefetched, never used) stays inside the allocation

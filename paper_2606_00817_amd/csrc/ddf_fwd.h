@@ -65,7 +65,7 @@ __device__ void encode_tile(const FwdArgs& a, int64_t ray0, E* X) {
   const int khalf = a.lay.k1_half;
   const bool split = sizeof(E) == 2;
   const int items = M * n_in * (1 + nf);
-  for (int idx = threadIdx.x; idx < items; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < items; idx += blockDim.x) {
     const int r = idx % M;
     const int rest = idx / M;
     const int j = rest % n_in;
@@ -107,7 +107,7 @@ __device__ void encode_tile(const FwdArgs& a, int64_t ray0, E* X) {
     }
   }
   const int pad = khalf - a.lay.n_feat;
-  for (int idx = threadIdx.x; idx < M * pad; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < M * pad; idx += blockDim.x) {
     const int r = idx % M, c = a.lay.n_feat + idx / M;
     X[r * LDX + c] = (E)0.f;
     if (split) X[r * LDX + khalf + c] = (E)0.f;

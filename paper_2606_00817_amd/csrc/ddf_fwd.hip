@@ -25,11 +25,12 @@ namespace ddf {
 // rt 32 + lane % 32.  Bias + ReLU, then either one vector write of the 4 values into the
 // LDS tile, or (last layer) the heads' partial dot products: one value per ray and head per
 // lane, the two lane halves added, then written per wave for the fixed-order final sum.
-template <class P, int WIDTH, int MODE>
-__device__ inline void epilogue_t(const FwdArgs& a, f32x16 (&acc)[Chain<P, WIDTH>::RT][Chain<P, WIDTH>::NT],
-                                  typename P::E* X, float (*headp)[Chain<P, WIDTH>::M][2], int l, int64_t ray0,
-                                  int64_t n_act, int nt0, int lane, int wave) {
-  using C = Chain<P, WIDTH>;
+template <class P, int WIDTH, int MODE, int WAVES>
+__device__ inline void epilogue_t(const FwdArgs& a,
+                                  f32x16 (&acc)[Chain<P, WIDTH, WAVES>::RT][Chain<P, WIDTH, WAVES>::NT],
+                                  typename P::E* X, float (*headp)[Chain<P, WIDTH, WAVES>::M][2], int l,
+                                  int64_t ray0, int64_t n_act, int nt0, int lane, int wave) {
+  using C = Chain<P, WIDTH, WAVES>;
   using E = typename P::E;
   constexpr int RT = C::RT, NT = C::NT, LDX = C::LDX;
   const float* bias = reinterpret_cast<const float*>(a.packed + a.lay.b_off) + (int64_t)l * WIDTH;
@@ -90,13 +91,13 @@ __device__ inline void epilogue_t(const FwdArgs& a, f32x16 (&acc)[Chain<P, WIDTH
   __syncthreads();
 }
 
-template <class P, int WIDTH, int MODE>
-__global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
-  using C = Chain<P, WIDTH>;
+template <class P, int WIDTH, int MODE, int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
+  using C = Chain<P, WIDTH, WAVES>;
   using E = typename P::E;
   constexpr int M = C::M, RT = C::RT, NT = C::NT, LDX = C::LDX;
   __shared__ __attribute__((aligned(16))) E X[C::XSIZE];
-  __shared__ float headp[kWaves][M][2];
+  __shared__ float headp[WAVES][M][2];
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
       C::template gemm<WIDTH / P::KBLK, kTrans>(acc, X, W, K / P::KBLK, nt0, lane);
     __syncthreads();   // every wave is done reading X
     if constexpr (kTrans) {
-      epilogue_t<P, WIDTH, MODE>(a, acc, X, headp, l, ray0, n_act, nt0, lane, wave);
+      epilogue_t<P, WIDTH, MODE, WAVES>(a, acc, X, headp, l, ray0, n_act, nt0, lane, wave);
       continue;
     }
 
@@ -201,12 +202,12 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
     __syncthreads();
   }
 
-  for (int r = threadIdx.x; r < M; r += kThreads) {
+  for (int r = threadIdx.x; r < M; r += WAVES * 64) {
     const int64_t g = ray0 + r;
     if (g >= n_act) continue;
     float z0 = hb[0], z1 = a.n_out > 1 ? hb[1] : 0.f;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) { z0 += headp[w][r][0]; z1 += headp[w][r][1]; }
+    for (int w = 0; w < WAVES; ++w) { z0 += headp[w][r][0]; z1 += headp[w][r][1]; }
     switch (MODE) {
       case kModeQuery:
       case kModeCalib:
@@ -227,16 +228,20 @@ __global__ __launch_bounds__(kThreads, 1) void fwd_kernel(FwdArgs a) {
   }
 }
 
+// Query modes run 8 waves (two per SIMD, 128 neurons each) when the width allows it, so
+// that one wave's matrix products cover the other's load and LDS latencies; the training
+// forward keeps 4 waves (its epilogue layout is the backward pass's).
 template <class P, int WIDTH>
 static hipError_t launch_t(const FwdArgs& a, int64_t n_tiles, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  const dim3 grid((unsigned)n_tiles), block(kThreads);
+  constexpr int QW = WIDTH >= 256 ? 8 : 4;
+  const dim3 grid((unsigned)n_tiles), bq(QW * 64), bt(kThreads);
   switch (a.mode) {
-    case kModeQuery: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeQuery>), grid, block, 0, st, a); break;
-    case kModeTrain: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrain>), grid, block, 0, st, a); break;
-    case kModeSdf: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeSdf>), grid, block, 0, st, a); break;
-    case kModeCalib: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeCalib>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrace>), grid, block, 0, st, a); break;
+    case kModeQuery: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeQuery, QW>), grid, bq, 0, st, a); break;
+    case kModeTrain: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrain, kWaves>), grid, bt, 0, st, a); break;
+    case kModeSdf: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeSdf, QW>), grid, bq, 0, st, a); break;
+    case kModeCalib: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeCalib, QW>), grid, bq, 0, st, a); break;
+    default: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrace, QW>), grid, bq, 0, st, a); break;
   }
   return hipGetLastError();
 }

@@ -26,6 +26,7 @@ struct TrainWs {
   int64_t scal;             // 64 bytes of scalars
   int64_t headp;            // head-gradient partials [kHeadChunks][2][width + 2]
   int64_t grad;             // fp32 [P] (used when the caller passes no gradient buffer)
+  int64_t dwpart;           // fp32 [8][P] weight-gradient partial sums of the ray ranges
   int64_t total;
   int esize;
 };
@@ -46,6 +47,7 @@ inline TrainWs train_ws(const ddf_net_desc& d, int64_t batch, size_t nparams) {
   w.scal = off; off = align256(off + 64);
   w.headp = off; off = align256(off + 4ll * kHeadChunks * 2 * (d.width + 2));
   w.grad = off; off = align256(off + 4 * (int64_t)nparams);
+  w.dwpart = off; off = align256(off + 32 * (int64_t)nparams);
   w.total = off;
   return w;
 }
@@ -299,24 +301,27 @@ __global__ __launch_bounds__(kThreads, 1) void bwd_chain_kernel(BwdArgs a) {
 struct DwArgs {
   const uint8_t* act;     // features slab then H_1..H_n
   const uint8_t* delta;   // delta_1..delta_n
-  float* grad;
+  float* grad;            // final gradient (one split) or the partials [splits][P]
   MasterOffsets mo;
-  int64_t R;
+  int64_t R;              // padded rows
+  int64_t P;              // parameters (stride of the partials)
   int n_hidden, width, k1_half, n_feat;
   int tiles_l0, tiles_l;  // workgroups for layer 1 and for every other hidden layer
-  int tn_l0;              // column tiles of layer 1
+  int tn_l0, tn_l;        // column tiles of layer 1 / of the other layers
+  int splits;             // ray ranges (blockIdx.y), each summed separately
 };
 
 // dW_l = sum_rays delta_l^T H_(l-1) (H_0 = the encoded features) and db_l = sum_rays delta_l,
-// for every hidden layer in one launch.  A workgroup owns a TM x 128 tile of one layer's
-// gradient and runs over all R rays: 4 waves in 2 x 2, each (TM/2) x 64, operands read in
-// matrix-core order straight from the [R / 8][cols][8] stores.  No split over rays, so
-// every sum has one fixed order.
-template <class P, int TM>
+// for every hidden layer in one launch.  A workgroup owns a TM x TN tile of one layer's
+// gradient over one of `splits` equal ray ranges: 4 waves in 2 x 2, each (TM/2) x (TN/2),
+// operands read in matrix-core order straight from the [R / 8][cols][8] stores through
+// buffer resources, three steps ahead in a ring of four.  Each (tile, range) sum has one
+// fixed order; with several ranges the partial sums are added in range order afterwards.
+template <class P, int TM, int TN>
 __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
-  using E = typename P::E;
   using Frag = typename P::AFrag;
   constexpr int RTW = TM / 64;   // 32-row tiles per wave
+  constexpr int CTW = TN / 64;   // 32-column tiles per wave
   constexpr int KB = P::KBLK;    // rays per step
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -329,13 +334,12 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
     blk -= a.tiles_l0;
     layer = 1 + blk / a.tiles_l; blk %= a.tiles_l;
     cols = a.width;
-    const int tnl = a.width / 128;
-    tm = blk / tnl; tn = blk % tnl;
+    tm = blk / a.tn_l; tn = blk % a.tn_l;
   }
   const int W = a.width;
   const int row0 = tm * TM + (wave >> 1) * (TM / 2);
-  const int col0 = tn * 128 + (wave & 1) * 64;
-  const int64_t es = sizeof(E);
+  const int col0 = tn * TN + (wave & 1) * (TN / 2);
+  constexpr int es = sizeof(typename P::E);
   const uint8_t* D = a.delta + (int64_t)layer * W * a.R * es;
   const uint8_t* Hb = layer == 0 ? a.act : a.act + ((int64_t)a.k1_half + (int64_t)(layer - 1) * W) * a.R * es;
   const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(D), (short)0,
@@ -345,42 +349,47 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
   // lane's byte offset inside a step: bf16 steps cover 16 rays (two 8-ray blocks, one per
   // lane half), fp32 steps 8 rays (one block, 4 rays per lane half)
   const int half = lane >> 5;
-  auto a_off = [&](int row) { return es == 2 ? (half * W + row) * 16 : row * 32 + half * 16; };
-  auto b_off = [&](int col) { return es == 2 ? (half * cols + col) * 16 : col * 32 + half * 16; };
-  const int a_step = W * 8 * (int)es * (KB / 8) ;     // bytes per step in the delta store
-  const int b_step = cols * 8 * (int)es * (KB / 8);
-  int ao[RTW], bo[2];
+  const int a_step = W * 8 * es * (KB / 8);      // bytes per step in the delta store
+  const int b_step = cols * 8 * es * (KB / 8);
+  int ao[RTW], bo[CTW];
 #pragma unroll
-  for (int r = 0; r < RTW; ++r) ao[r] = a_off(row0 + r * 32 + (lane & 31));
+  for (int r = 0; r < RTW; ++r) {
+    const int row = row0 + r * 32 + (lane & 31);
+    ao[r] = es == 2 ? (half * W + row) * 16 : row * 32 + half * 16;
+  }
 #pragma unroll
-  for (int c = 0; c < 2; ++c) bo[c] = b_off(col0 + c * 32 + (lane & 31));
+  for (int c = 0; c < CTW; ++c) {
+    const int col = col0 + c * 32 + (lane & 31);
+    bo[c] = es == 2 ? (half * cols + col) * 16 : col * 32 + half * 16;
+  }
 
-  f32x16 acc[RTW][2];
+  f32x16 acc[RTW][CTW];
 #pragma unroll
-  for (int r = 0; r < RTW; ++r) { acc[r][0] = f32x16{}; acc[r][1] = f32x16{}; }
+  for (int r = 0; r < RTW; ++r)
+#pragma unroll
+    for (int c = 0; c < CTW; ++c) acc[r][c] = f32x16{};
   float rsum[RTW];
 #pragma unroll
   for (int r = 0; r < RTW; ++r) rsum[r] = 0.f;
   const bool do_bias = (tn == 0) && ((wave & 1) == 0);
 
-  // Loads run three steps ahead in a ring of four (steps is a multiple of 4: R is a multiple
-  // of 128); the loads past the end are bounds-checked by the buffer resources.
-  const int steps = (int)(a.R / KB);
-  Frag A[4][RTW], B[4][2];
+  const int steps = (int)(a.R / KB) / a.splits;   // a multiple of 4
+  const int s0 = blockIdx.y * steps;
+  Frag A[4][RTW], B[4][CTW];
   auto load = [&](int slot, int s) {
-    const int sa = s * a_step, sb = s * b_step;
+    const int sa = (s0 + s) * a_step, sb = (s0 + s) * b_step;
 #pragma unroll
     for (int r = 0; r < RTW; ++r)
       A[slot][r] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rd, ao[r], sa, 0));
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < CTW; ++c)
       B[slot][c] = __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(rh, bo[c], sb, 0));
   };
   auto compute = [&](int slot) {
 #pragma unroll
     for (int r = 0; r < RTW; ++r) {
-      P::mma(acc[r][0], A[slot][r], B[slot][0]);
-      P::mma(acc[r][1], A[slot][r], B[slot][1]);
+#pragma unroll
+      for (int c = 0; c < CTW; ++c) P::mma(acc[r][c], A[slot][r], B[slot][c]);
       if (do_bias)
 #pragma unroll
         for (int j = 0; j < KB / 2; ++j) rsum[r] += (float)A[slot][r][j];
@@ -409,11 +418,12 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
   }
 
   const int fan_in = layer == 0 ? a.n_feat : W;
-  float* gw = a.grad + a.mo.w[layer];
+  float* out = a.grad + (a.splits > 1 ? (int64_t)blockIdx.y * a.P : 0);
+  float* gw = out + a.mo.w[layer];
 #pragma unroll
   for (int r = 0; r < RTW; ++r)
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
+    for (int c = 0; c < CTW; ++c) {
       const int col = col0 + c * 32 + (lane & 31);
       if (col < fan_in) {
 #pragma unroll
@@ -424,12 +434,22 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
       }
     }
   if (do_bias) {
-    float* gb = a.grad + a.mo.b[layer];
+    float* gb = out + a.mo.b[layer];
 #pragma unroll
     for (int r = 0; r < RTW; ++r) {
       const float tot = rsum[r] + __shfl_xor(rsum[r], 32);   // the two lane halves hold disjoint rays
       if (lane < 32) gb[row0 + r * 32 + lane] = tot;
     }
+  }
+}
+
+// grad[i] = sum over ray ranges s (in order) of partial[s][i], for the hidden layers' slice
+// [0, n) of the parameter vector (the head gradients are written directly).
+__global__ void sum_splits_kernel(const float* part, int splits, int64_t P, int64_t n, float* grad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part[(int64_t)k * P + i];
+    grad[i] = s;
   }
 }
 
@@ -591,18 +611,33 @@ static hipError_t launch_bwd(const ddf_net_desc& d, const BwdArgs& b, hipStream_
   return hipGetLastError();
 }
 
+// Ray ranges of the weight-gradient launch: enough workgroups for two per CU, and a step
+// count per range that stays a multiple of 4.
+static int dw_splits(int tiles, int64_t steps) {
+  int s = 1;
+  while (s < 8 && tiles * s < 512 && (steps % (4 * 2 * s)) == 0) s *= 2;
+  return s;
+}
+
 template <class P>
 static hipError_t launch_dw(const ddf_net_desc& d, DwArgs& a, hipStream_t st) {
-  const int TM = d.width >= 256 ? 256 : 128;
-  a.tn_l0 = (a.k1_half + 127) / 128;
-  a.tiles_l0 = (d.width / TM) * a.tn_l0;
-  a.tiles_l = (d.width / TM) * (d.width / 128);
-  const unsigned blocks = (unsigned)(a.tiles_l0 + (d.n_hidden - 1) * a.tiles_l);
-  if (TM == 256)
-    hipLaunchKernelGGL((dw_kernel<P, 256>), dim3(blocks), dim3(kThreads), 0, st, a);
+  const int T = d.width >= 512 ? 256 : 128;   // square tiles
+  a.tn_l0 = (a.k1_half + T - 1) / T;
+  a.tn_l = d.width / T;
+  a.tiles_l0 = (d.width / T) * a.tn_l0;
+  a.tiles_l = (d.width / T) * a.tn_l;
+  const int tiles = a.tiles_l0 + (d.n_hidden - 1) * a.tiles_l;
+  const dim3 grid((unsigned)tiles, (unsigned)a.splits);
+  if (T == 256)
+    hipLaunchKernelGGL((dw_kernel<P, 256, 256>), grid, dim3(kThreads), 0, st, a);
   else
-    hipLaunchKernelGGL((dw_kernel<P, 128>), dim3(blocks), dim3(kThreads), 0, st, a);
+    hipLaunchKernelGGL((dw_kernel<P, 128, 128>), grid, dim3(kThreads), 0, st, a);
   return hipGetLastError();
+}
+
+static int dw_tiles(const ddf_net_desc& d, int k1_half) {
+  const int T = d.width >= 512 ? 256 : 128;
+  return (d.width / T) * ((k1_half + T - 1) / T) + (d.n_hidden - 1) * (d.width / T) * (d.width / T);
 }
 
 // Backward from the logit gradients already in ws (dz_t, dz_xi) into grad.
@@ -619,11 +654,18 @@ static int run_backward(const ddf_net_desc& d, const void* packed, const TrainWs
   hipError_t e = d.precision == DDF_FP32 ? launch_bwd<PF32>(d, b, st) : launch_bwd<PBF16>(d, b, st);
   if (e != hipSuccess) return hip_status(e, "backward chain launch");
   DwArgs a{};
-  a.act = ws + w.act; a.delta = ws + w.delta; a.grad = grad;
+  a.act = ws + w.act; a.delta = ws + w.delta;
   a.mo = master_offsets(d);
-  a.R = w.R; a.n_hidden = d.n_hidden; a.width = d.width; a.k1_half = L.k1_half; a.n_feat = L.n_feat;
+  a.R = w.R; a.P = (int64_t)param_count_of(d);
+  a.n_hidden = d.n_hidden; a.width = d.width; a.k1_half = L.k1_half; a.n_feat = L.n_feat;
+  a.splits = dw_splits(dw_tiles(d, L.k1_half), w.R / (d.precision == DDF_FP32 ? 8 : 16));
+  a.grad = a.splits > 1 ? reinterpret_cast<float*>(ws + w.dwpart) : grad;
   e = d.precision == DDF_FP32 ? launch_dw<PF32>(d, a, st) : launch_dw<PBF16>(d, a, st);
   if (e != hipSuccess) return hip_status(e, "weight-gradient launch");
+  if (a.splits > 1) {
+    sum_splits_kernel<<<2048, 256, 0, st>>>(a.grad, a.splits, a.P, a.mo.w[d.n_hidden], grad);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_status(e, "weight-gradient sum launch");
+  }
   const int64_t hslab = ((int64_t)L.k1_half + (int64_t)(d.n_hidden - 1) * d.width) * w.R * w.esize;
   const dim3 hb((unsigned)(d.width / 32 + 1), kHeadChunks);
   const MasterOffsets mo = master_offsets(d);
