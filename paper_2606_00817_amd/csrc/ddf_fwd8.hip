@@ -105,16 +105,55 @@ __device__ inline void gemm_f8(f32x16 (&acc)[kRT8][NTP], const uint8_t* X, const
   }
 }
 
+// The same product with the activation operand streamed one 32-ray tile at a time (the
+// next tile's LDS read overlaps the current tile's products): fewer registers, for the
+// 8-wave layout where two waves share a SIMD's register file.
+template <int NTP, int LDX, int KB>
+__device__ inline void gemm_f8_stream(f32x16 (&acc)[kRT8][NTP], const uint8_t* X, const void* W, int tile0,
+                                      int lane, int width) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, width * KB * 64, 0x00020000);
+  const int voff = lane * 32;
+  const int base = tile0 * KB * 2048;
+  const uint8_t* xrow = X + (lane & 31) * LDX + 32 * (lane >> 5);
+  i32x8 b[3][NTP];
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
+#pragma unroll
+    for (int t = 0; t < NTP; ++t) b[st][t] = buf_b8(rs, voff, base + (t * KB + st) * 2048);
+  i32x8 av[2];
+  av[0] = lds_a8(xrow);
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+#pragma unroll
+    for (int t = 0; t < NTP; ++t) b[(k + 2) % 3][t] = buf_b8(rs, voff, base + (t * KB + k + 2) * 2048);
+#pragma unroll
+    for (int rt = 0; rt < kRT8; ++rt) {
+      const int i = k * kRT8 + rt;            // running tile index: parity picks the buffer
+      if (rt + 1 < kRT8)
+        av[(i + 1) & 1] = lds_a8(xrow + (rt + 1) * 32 * LDX + k * 64);
+      else if (k + 1 < KB)
+        av[(i + 1) & 1] = lds_a8(xrow + (k + 1) * 64);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < NTP; ++t)
+        acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(b[k % 3][t], av[i & 1], acc[rt][t], 0, 0, 0,
+                                                                     127, 0, 127);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 }  // namespace
 
-template <int WIDTH, int MODE>
-__global__ __launch_bounds__(kThreads, 1) void fwd8_kernel(FwdArgs a) {
-  constexpr int NTW = WIDTH / 32 / kWaves;   // 32-neuron tiles per wave
+template <int WIDTH, int MODE, int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
+  constexpr int NTW = WIDTH / 32 / WAVES;    // 32-neuron tiles per wave
   constexpr int NTP = NTW / 2;               // tiles per pass
   constexpr int LDX = WIDTH + 16;            // e4m3 row stride (bytes)
   constexpr int XBYTES = kM8 * LDX > kM8 * kLDG * 2 ? kM8 * LDX : kM8 * kLDG * 2;
   __shared__ __attribute__((aligned(16))) uint8_t smem[XBYTES];
-  __shared__ float headp[kWaves][kM8][2];
+  __shared__ float headp[WAVES][kM8][2];
   uint8_t* X = smem;
   __bf16* G = reinterpret_cast<__bf16*>(smem);
 
@@ -158,7 +197,12 @@ __global__ __launch_bounds__(kThreads, 1) void fwd8_kernel(FwdArgs a) {
       if (l == 0)
         gemm_l1<NTP>(acc, G, W, a.lay.k1 / 16, tile0, lane, WIDTH);
       else
-        gemm_f8<NTP, LDX, WIDTH / 64>(acc, X, W, tile0, lane, WIDTH);
+      {
+        if constexpr (WAVES == 8)
+          gemm_f8_stream<NTP, LDX, WIDTH / 64>(acc, X, W, tile0, lane, WIDTH);
+        else
+          gemm_f8<NTP, LDX, WIDTH / 64>(acc, X, W, tile0, lane, WIDTH);
+      }
       if (p == 1) {
         __syncthreads();   // every wave is done reading this layer's input
         if (!last) {
@@ -223,12 +267,12 @@ __global__ __launch_bounds__(kThreads, 1) void fwd8_kernel(FwdArgs a) {
     __syncthreads();
   }
 
-  for (int r = threadIdx.x; r < kM8; r += kThreads) {
+  for (int r = threadIdx.x; r < kM8; r += WAVES * 64) {
     const int64_t g = ray0 + r;
     if (g >= n_act) continue;
     float z0 = hb[0], z1 = a.n_out > 1 ? hb[1] : 0.f;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) { z0 += headp[w][r][0]; z1 += headp[w][r][1]; }
+    for (int w = 0; w < WAVES; ++w) { z0 += headp[w][r][0]; z1 += headp[w][r][1]; }
     if (MODE == kModeQuery) {
       a.out0[g] = softplusf_(z0);
       a.out1[g] = sigmoidf_(z1);
@@ -243,11 +287,12 @@ __global__ __launch_bounds__(kThreads, 1) void fwd8_kernel(FwdArgs a) {
 template <int WIDTH>
 static hipError_t launch8_t(const FwdArgs& a, int64_t n_tiles, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  const dim3 grid((unsigned)n_tiles), block(kThreads);
+  constexpr int QW = WIDTH >= 512 ? 8 : 4;   // two waves per SIMD where each keeps >= 2 tiles per pass
+  const dim3 grid((unsigned)n_tiles), block(QW * 64);
   switch (a.mode) {
-    case kModeQuery: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeQuery>), grid, block, 0, st, a); break;
-    case kModeSdf: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeSdf>), grid, block, 0, st, a); break;
-    case kModeTrace: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeTrace>), grid, block, 0, st, a); break;
+    case kModeQuery: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeQuery, QW>), grid, block, 0, st, a); break;
+    case kModeSdf: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeSdf, QW>), grid, block, 0, st, a); break;
+    case kModeTrace: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeTrace, QW>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
