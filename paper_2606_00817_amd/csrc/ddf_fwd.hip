@@ -228,17 +228,16 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
   }
 }
 
-// Query modes run 8 waves (two per SIMD, 128 neurons each) when the width allows it, so
-// that one wave's matrix products cover the other's load and LDS latencies; the training
-// forward keeps 4 waves (its epilogue layout is the backward pass's).
+// 8 waves (two per SIMD, 128 neurons each) when the width allows it, so that one wave's
+// matrix products cover the other's load and LDS latencies.
 template <class P, int WIDTH>
 static hipError_t launch_t(const FwdArgs& a, int64_t n_tiles, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
   constexpr int QW = WIDTH >= 256 ? 8 : 4;
-  const dim3 grid((unsigned)n_tiles), bq(QW * 64), bt(kThreads);
+  const dim3 grid((unsigned)n_tiles), bq(QW * 64);
   switch (a.mode) {
     case kModeQuery: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeQuery, QW>), grid, bq, 0, st, a); break;
-    case kModeTrain: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrain, kWaves>), grid, bt, 0, st, a); break;
+    case kModeTrain: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrain, QW>), grid, bq, 0, st, a); break;
     case kModeSdf: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeSdf, QW>), grid, bq, 0, st, a); break;
     case kModeCalib: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeCalib, QW>), grid, bq, 0, st, a); break;
     default: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrace, QW>), grid, bq, 0, st, a); break;

@@ -221,9 +221,9 @@ struct BwdArgs {
 // delta_n = (dz_t w_t + dz_xi w_xi) * 1[H_n > 0]; then for l = n..2:
 // delta_(l-1) = (delta_l W_l) * 1[H_(l-1) > 0], the product on the matrix cores with the
 // transposed weight blocks, the running delta resident in LDS.  Every delta_l is stored.
-template <class P, int WIDTH>
-__global__ __launch_bounds__(kThreads, 1) void bwd_chain_kernel(BwdArgs a) {
-  using C = Chain<P, WIDTH>;
+template <class P, int WIDTH, int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
+  using C = Chain<P, WIDTH, WAVES>;
   using E = typename P::E;
   constexpr int M = C::M, RT = C::RT, NT = C::NT, LDX = C::LDX;
   __shared__ __attribute__((aligned(16))) E X[C::XSIZE];
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kThreads, 1) void bwd_chain_kernel(BwdArgs a) {
   {
     const E* Hn = H + (int64_t)(a.n_hidden - 1) * slab;
     E* Dn = delta + (int64_t)(a.n_hidden - 1) * slab;
-    for (int idx = threadIdx.x; idx < M * WIDTH; idx += kThreads) {
+    for (int idx = threadIdx.x; idx < M * WIDTH; idx += WAVES * 64) {
       const int q = idx & 7;
       const int j = (idx >> 3) % WIDTH;
       const int rb = (idx >> 3) / WIDTH;
@@ -603,10 +603,10 @@ template <class P>
 static hipError_t launch_bwd(const ddf_net_desc& d, const BwdArgs& b, hipStream_t st) {
   const unsigned blocks = (unsigned)(b.R / P::M);
   switch (d.width) {
-    case 128: hipLaunchKernelGGL((bwd_chain_kernel<P, 128>), dim3(blocks), dim3(kThreads), 0, st, b); break;
-    case 256: hipLaunchKernelGGL((bwd_chain_kernel<P, 256>), dim3(blocks), dim3(kThreads), 0, st, b); break;
-    case 512: hipLaunchKernelGGL((bwd_chain_kernel<P, 512>), dim3(blocks), dim3(kThreads), 0, st, b); break;
-    default: hipLaunchKernelGGL((bwd_chain_kernel<P, 1024>), dim3(blocks), dim3(kThreads), 0, st, b); break;
+    case 128: hipLaunchKernelGGL((bwd_chain_kernel<P, 128, 4>), dim3(blocks), dim3(256), 0, st, b); break;
+    case 256: hipLaunchKernelGGL((bwd_chain_kernel<P, 256, 8>), dim3(blocks), dim3(512), 0, st, b); break;
+    case 512: hipLaunchKernelGGL((bwd_chain_kernel<P, 512, 8>), dim3(blocks), dim3(512), 0, st, b); break;
+    default: hipLaunchKernelGGL((bwd_chain_kernel<P, 1024, 8>), dim3(blocks), dim3(512), 0, st, b); break;
   }
   return hipGetLastError();
 }
