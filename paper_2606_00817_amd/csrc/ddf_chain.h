@@ -47,63 +47,82 @@ struct Chain {
     return __builtin_bit_cast(BFrag, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0));
   }
 
-  // acc[rt][t] += X[rt rows][0:K] * W[(nt0 + t) neuron tile][0:K]^T.  The weight blocks of
-  // one layer are read through a buffer resource: per-lane offset lane * 16 bytes, the
-  // block offset ((nt0 + t) KB + k) * 1 KiB is wave-uniform.  Loads run three blocks
-  // ahead in a ring of four; KB is a multiple of 4, and the loads past the end of the
-  // layer are bounds-checked by the buffer resource (they return zeros, never used).
-  // KBC > 0 fixes KB at compile time (hidden layers): the k loop is then fully unrolled.
+  // The ring of weight blocks a wave keeps in flight: four stages of NT blocks.
+  struct Ring {
+    BFrag b0[NT], b1[NT], b2[NT], b3[NT];
+  };
+
+  static __device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* W, int KB) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, WIDTH * KB * 32, 0x00020000);
+  }
+
+  // Block (t, k) of the wave's tiles, at byte ((nt0 + t) KB + k) * 1 KiB + lane * 16 of the
+  // layer: the per-lane part and (k mod 4) KiB go into the vector offset (the constant part
+  // folds into the instruction's immediate), the wave-uniform tile and k / 4 part into the
+  // scalar offset, so that a fully unrolled k loop needs one scalar offset per four blocks.
+  static __device__ inline BFrag ld(__amdgpu_buffer_rsrc_t rs, int voff, int base, int tstride, int t, int k) {
+    return load_b(rs, voff + (k & 3) * 1024, base + t * tstride + (k >> 2) * 4096);
+  }
+
+  // First three stages of a layer's weight blocks (issued ahead of time, e.g. before the
+  // previous layer's epilogue).
+  static __device__ inline void preload(Ring& r, const void* W, int KB, int nt0, int lane) {
+    const __amdgpu_buffer_rsrc_t rs = rsrc(W, KB);
+    const int voff = lane * 16, base = nt0 * KB * 1024, tstride = KB * 1024;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      r.b0[t] = ld(rs, voff, base, tstride, t, 0);
+      r.b1[t] = ld(rs, voff, base, tstride, t, 1);
+      r.b2[t] = ld(rs, voff, base, tstride, t, 2);
+    }
+  }
+
   // TRANS = false: acc[rt][t] = X_tile * W_tile^T (rows rays, columns neurons).
   // TRANS = true : acc[rt][t] = W_tile * X_tile^T (rows neurons, columns rays): the same
   //   operand blocks with their matrix-core roles swapped, so that each lane ends up with 4
   //   consecutive neurons of one ray per register group.
+  // acc[rt][t] accumulates over the wave's neuron tile (nt0 + t) and all K inputs.  The weight
+  // blocks of one layer are read through a buffer resource three blocks ahead in a ring of
+  // four (the first three already issued by preload); KB is a multiple of 4, and the loads
+  // past the end of the layer are bounds-checked by the buffer resource (they return zeros,
+  // never used).  KBC > 0 fixes KB at compile time (hidden layers): the k loop is then fully
+  // unrolled.
   template <int KBC, bool TRANS = false>
   static __device__ inline void gemm(f32x16 (&acc)[RT][NT], const E* X, const void* W, int KB_rt,
-                                     int nt0, int lane) {
+                                     int nt0, int lane, Ring& r) {
     const int KB = KBC > 0 ? KBC : KB_rt;
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, WIDTH * KB * 32, 0x00020000);
-    const int voff = lane * 16;
-    const int base = nt0 * KB * 1024;
-    const int tstride = KB * 1024;
+    const __amdgpu_buffer_rsrc_t rs = rsrc(W, KB);
+    const int voff = lane * 16, base = nt0 * KB * 1024, tstride = KB * 1024;
     const E* xrow = X + (lane & 31) * LDX + (P::KBLK / 2) * (lane >> 5);
-    BFrag b0[NT], b1[NT], b2[NT], b3[NT];
     AFrag a0[RT], a1[RT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) {
-      b0[t] = load_b(rs, voff, base + t * tstride);
-      b1[t] = load_b(rs, voff, base + t * tstride + 1024);
-      b2[t] = load_b(rs, voff, base + t * tstride + 2048);
-    }
     load_a(a0, xrow, 0);
 #pragma unroll (KBC > 0 ? KBC / 4 : 1)
     for (int k = 0; k < KB; k += 4) {
-      const int kb = base + k * 1024;
       // each quarter: issue the weight loads three blocks ahead and the LDS read of the next
       // block's activations, then the matrix products of this block
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b3[t] = load_b(rs, voff, kb + t * tstride + 3 * 1024);
+      for (int t = 0; t < NT; ++t) r.b3[t] = ld(rs, voff, base, tstride, t, k + 3);
       load_a(a1, xrow, k + 1);
       __builtin_amdgcn_sched_barrier(0);
-      mma_all<TRANS>(acc, a0, b0);
+      mma_all<TRANS>(acc, a0, r.b0);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b0[t] = load_b(rs, voff, kb + t * tstride + 4 * 1024);
+      for (int t = 0; t < NT; ++t) r.b0[t] = ld(rs, voff, base, tstride, t, k + 4);
       load_a(a0, xrow, k + 2);
       __builtin_amdgcn_sched_barrier(0);
-      mma_all<TRANS>(acc, a1, b1);
+      mma_all<TRANS>(acc, a1, r.b1);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b1[t] = load_b(rs, voff, kb + t * tstride + 5 * 1024);
+      for (int t = 0; t < NT; ++t) r.b1[t] = ld(rs, voff, base, tstride, t, k + 5);
       load_a(a1, xrow, k + 3);
       __builtin_amdgcn_sched_barrier(0);
-      mma_all<TRANS>(acc, a0, b2);
+      mma_all<TRANS>(acc, a0, r.b2);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b2[t] = load_b(rs, voff, kb + t * tstride + 6 * 1024);
+      for (int t = 0; t < NT; ++t) r.b2[t] = ld(rs, voff, base, tstride, t, k + 6);
       load_a(a0, xrow, k + 4);   // one block past the end on the last pass: inside the row padding
       __builtin_amdgcn_sched_barrier(0);
-      mma_all<TRANS>(acc, a1, b3);
+      mma_all<TRANS>(acc, a1, r.b3);
       __builtin_amdgcn_sched_barrier(0);
     }
   }

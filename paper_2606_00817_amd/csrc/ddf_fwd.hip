@@ -114,6 +114,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
   const float* hw = reinterpret_cast<const float*>(a.packed + a.lay.head_w_off);
   const float* hb = reinterpret_cast<const float*>(a.packed + a.lay.head_b_off);
   const int nt0 = wave * NT;
+  typename C::Ring ring;
 
   for (int l = 0; l < a.n_hidden; ++l) {
     const int K = l == 0 ? a.lay.k1 : WIDTH;
@@ -124,10 +125,16 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
     constexpr bool kTrans = MODE != kModeTrain;
-    if (l == 0)
-      C::template gemm<0, kTrans>(acc, X, W, K / P::KBLK, nt0, lane);
-    else
-      C::template gemm<WIDTH / P::KBLK, kTrans>(acc, X, W, K / P::KBLK, nt0, lane);
+    // query modes issue a layer's first weight blocks before the previous layer's epilogue
+    // (they do not depend on its output); the training epilogue has no registers to spare
+    if (l == 0) {
+      C::preload(ring, W, K / P::KBLK, nt0, lane);
+      C::template gemm<0, kTrans>(acc, X, W, K / P::KBLK, nt0, lane, ring);
+    } else {
+      if (!kTrans) C::preload(ring, W, WIDTH / P::KBLK, nt0, lane);
+      C::template gemm<WIDTH / P::KBLK, kTrans>(acc, X, W, K / P::KBLK, nt0, lane, ring);
+    }
+    if (kTrans && l + 1 < a.n_hidden) C::preload(ring, a.packed + a.lay.w_off[l + 1], WIDTH / P::KBLK, nt0, lane);
     __syncthreads();   // every wave is done reading X
     if constexpr (kTrans) {
       epilogue_t<P, WIDTH, MODE, WAVES>(a, acc, X, headp, l, ray0, n_act, nt0, lane, wave);

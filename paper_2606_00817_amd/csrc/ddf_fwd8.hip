@@ -37,9 +37,11 @@ __device__ inline i32x8 buf_b8(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
   return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
-__device__ inline uint8_t to_e4m3(float x) {
-  x = fminf(fmaxf(x, -448.f), 448.f);        // saturate, then round to nearest even
-  return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, x, 0, false) & 0xff);
+// Four non-negative values, already divided by the next layer's scale, as four e4m3 codes in
+// one word (element i in byte i): saturate at 448, then round to nearest even.
+__device__ inline uint32_t pack_e4m3(float y0, float y1, float y2, float y3) {
+  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(fminf(y0, 448.f), fminf(y1, 448.f), 0, false);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(fminf(y2, 448.f), fminf(y3, 448.f), lo, true);
 }
 
 // acc[rt][t] += G[rt rows][0:K1] * W1[tile (tile0 + t)][0:K1]^T   (bf16 operands)
@@ -177,6 +179,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
     const bool last = (l + 1 == a.n_hidden);
     const float dq = scales[4 * l + kDequant];
     const float qn = scales[4 * l + kQuantNext];
+    const float dqn = dq * qn;
     const float* bias = bias_all + (int64_t)l * WIDTH;
     const void* W = a.packed + a.lay.w_off[l];
     // Operand roles are swapped (weights as the first matrix-core operand): register group q
@@ -203,9 +206,34 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
         else
           gemm_f8<NTP, LDX, WIDTH / 64>(acc, X, W, tile0, lane, WIDTH);
       }
-      if (p == 1) {
-        __syncthreads();   // every wave is done reading this layer's input
-        if (!last) {
+      if (p == 1) __syncthreads();   // every wave is done reading this layer's input
+      // the two epilogues are separate uniform branches, so that neither carries the
+      // other's tests inside its unrolled loops
+      if (last) {
+        // heads from the fp32 output of the last hidden layer (a single-output network reads
+        // head 0 twice and drops the second sum)
+        const float* hw1 = a.n_out > 1 ? hw + WIDTH : hw;
+#pragma unroll
+        for (int t = 0; t < NTP; ++t) {
+          const int nb = (tile0 + t) * 32 + 4 * (lane >> 5);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const f32x4 b4 = *reinterpret_cast<const f32x4*>(bias + nb + 8 * q);
+            const f32x4 w0 = *reinterpret_cast<const f32x4*>(hw + nb + 8 * q);
+            const f32x4 w1 = *reinterpret_cast<const f32x4*>(hw1 + nb + 8 * q);
+#pragma unroll
+            for (int rt = 0; rt < kRT8; ++rt) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const float y = fmaxf(fmaf(acc[rt][t][4 * q + i], dq, b4[i]), 0.f);
+                hp0[rt] = fmaf(w0[i], y, hp0[rt]);
+                hp1[rt] = fmaf(w1[i], y, hp1[rt]);
+              }
+            }
+          }
+        }
+      } else {
+        if (p == 1) {
 #pragma unroll
           for (int rt = 0; rt < kRT8; ++rt)
 #pragma unroll
@@ -216,41 +244,31 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
                 *reinterpret_cast<uint32_t*>(X + (rt * 32 + (lane & 31)) * LDX + nb + 8 * q) = hold[rt][t][q];
             }
         }
-      }
 #pragma unroll
-      for (int t = 0; t < NTP; ++t) {
-        const int nb = (tile0 + t) * 32 + 4 * (lane >> 5);
+        for (int t = 0; t < NTP; ++t) {
+          const int nb = (tile0 + t) * 32 + 4 * (lane >> 5);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const f32x4 b4 = *reinterpret_cast<const f32x4*>(bias + nb + 8 * q);
-          f32x4 w0 = {}, w1 = {};
-          if (last) {
-            w0 = *reinterpret_cast<const f32x4*>(hw + nb + 8 * q);
-            if (a.n_out > 1) w1 = *reinterpret_cast<const f32x4*>(hw + WIDTH + nb + 8 * q);
-          }
+          for (int q = 0; q < 4; ++q) {
+            // relu(acc dq + b) / s_A,next in one rounding: the scales are powers of two, so
+            // fma(acc, dq qn, b qn) is exactly qn fma(acc, dq, b)
+            const f32x4 b4 = *reinterpret_cast<const f32x4*>(bias + nb + 8 * q);
+            f32x4 bq;
 #pragma unroll
-          for (int rt = 0; rt < kRT8; ++rt) {
-            float y[4];
+            for (int i = 0; i < 4; ++i) bq[i] = b4[i] * qn;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) y[i] = fmaxf(fmaf(acc[rt][t][4 * q + i], dq, b4[i]), 0.f);
-            if (last) {
+            for (int rt = 0; rt < kRT8; ++rt) {
+              float y[4];
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                hp0[rt] = fmaf(w0[i], y[i], hp0[rt]);
-                hp1[rt] = fmaf(w1[i], y[i], hp1[rt]);
-              }
-            } else {
-              uint32_t w = 0;
-#pragma unroll
-              for (int i = 0; i < 4; ++i) w |= (uint32_t)to_e4m3(y[i] * qn) << (8 * i);
+              for (int i = 0; i < 4; ++i) y[i] = fmaxf(fmaf(acc[rt][t][4 * q + i], dqn, bq[i]), 0.f);
+              const uint32_t w = pack_e4m3(y[0], y[1], y[2], y[3]);
               if (p == 0)
                 hold[rt][t][q] = w;
               else
                 *reinterpret_cast<uint32_t*>(X + (rt * 32 + (lane & 31)) * LDX + nb + 8 * q) = w;
             }
           }
+          __builtin_amdgcn_sched_barrier(0);
         }
-        __builtin_amdgcn_sched_barrier(0);
       }
     }
     if (last) {

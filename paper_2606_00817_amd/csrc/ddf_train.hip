@@ -252,15 +252,18 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
       Dn[gi] = (E)d;
     }
   }
-  __syncthreads();
   const int nt0 = wave * NT;
+  typename C::Ring ring;
+  if (a.n_hidden > 1) C::preload(ring, a.packed + a.lay.wt_off[a.n_hidden - 1], WIDTH / P::KBLK, nt0, lane);
+  __syncthreads();
   for (int l = a.n_hidden - 1; l >= 1; --l) {
     f32x16 acc[RT][NT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
-    C::template gemm<WIDTH / P::KBLK>(acc, X, a.packed + a.lay.wt_off[l], WIDTH / P::KBLK, nt0, lane);
+    C::template gemm<WIDTH / P::KBLK>(acc, X, a.packed + a.lay.wt_off[l], WIDTH / P::KBLK, nt0, lane, ring);
+    if (l > 1) C::preload(ring, a.packed + a.lay.wt_off[l - 1], WIDTH / P::KBLK, nt0, lane);
     __syncthreads();
     const E* Hm = H + (int64_t)(l - 1) * slab;        // H_(l-1): output of hidden layer l - 1
     E* Dm = delta + (int64_t)(l - 1) * slab;
