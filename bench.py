@@ -28,6 +28,41 @@ FLOP_PER_RAY = {}          # algorithmic FLOPs per ray and net (no padding, no h
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}   # MI355X dense matrix peaks
 N_RAYS = 1 << 20
 
+# HBM traffic of one launch of the timed query kernel, from two rocprofv3 counter passes over
+# this workload (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same
+# counter reads for a 1 GiB device copy in the same run (FETCH_SIZE reads 524,306 KiB for
+# 1,048,576 KiB fetched: x2; WRITE_SIZE reads 1,048,576 KiB: x1).  The figures hold for the
+# kernel sources they were taken on (sha256 over KERNEL_SOURCES); after any change to those
+# files the bench reports null until the counters are taken again.
+COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
+TRAFFIC_KIB = {
+    "bf16": {"FETCH_SIZE": 5925032, "WRITE_SIZE": 8192,
+             "sha256": "6f15d0e0b63773c5d49a6062fb599a1ca37a46420f8ca63324ce49346521ea11"},
+    "fp8": {"FETCH_SIZE": 1625817, "WRITE_SIZE": 329993, "sha256": None},
+}
+KERNEL_SOURCES = {
+    "fp32": ["ddf_fwd.hip", "ddf_chain.h", "ddf_fwd.h", "ddf_internal.h"],
+    "bf16": ["ddf_fwd.hip", "ddf_chain.h", "ddf_fwd.h", "ddf_internal.h"],
+    "fp8": ["ddf_fwd8.hip", "ddf_fwd.h", "ddf_internal.h"],
+}
+
+
+def kernel_source_hash(prec):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[prec]:
+        with open(os.path.join(HERE, "paper_2606_00817_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes(prec):
+    """Scaled HBM bytes per launch, or None when unmeasured or the kernel changed since."""
+    rec = TRAFFIC_KIB.get(prec)
+    if rec is None or rec["sha256"] != kernel_source_hash(prec):
+        return None
+    return int(sum(rec[c] * COUNTER_SCALE[c] for c in COUNTER_SCALE) * 1024)
+
 
 def flop_per_ray(desc):
     f = 2 * desc.width * desc.n_feat + 2 * (desc.n_hidden - 1) * desc.width * desc.width
@@ -160,7 +195,7 @@ def main():
         "config": {"workload": "2^20 shadow rays, 256-primitive scene, 12x1024 DDF (L=10, 126 features)",
                    "rays": N_RAYS, "net": "126-1024x12-2", "precision": prec},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS[prec], "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS[prec], "traffic": traffic_bytes(prec),
                      "kernel": f"fwd_kernel ({prec}), one launch per step",
                      "flop_per_launch": fpr * N_RAYS},
     }

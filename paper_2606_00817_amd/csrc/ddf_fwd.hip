@@ -22,18 +22,18 @@ namespace ddf {
 
 // Epilogue of a layer computed with swapped operand roles (query modes): register group q of
 // tile (rt, t) holds neurons (nt0 + t) 32 + 8 q + 4 (lane / 32) + i, i < 4, of ray
-// rt 32 + lane % 32.  Bias + ReLU, then either one vector write of the 4 values into the
+// rt 32 + lane % 32.  Bias (read from the wave's LDS copy) + ReLU, then either one vector write of the 4 values into the
 // LDS tile, or (last layer) the heads' partial dot products: one value per ray and head per
 // lane, the two lane halves added, then written per wave for the fixed-order final sum.
 template <class P, int WIDTH, int MODE, int WAVES>
 __device__ inline void epilogue_t(const FwdArgs& a,
                                   f32x16 (&acc)[Chain<P, WIDTH, WAVES>::RT][Chain<P, WIDTH, WAVES>::NT],
-                                  typename P::E* X, float (*headp)[Chain<P, WIDTH, WAVES>::M][2], int l,
-                                  int64_t ray0, int64_t n_act, int nt0, int lane, int wave) {
+                                  typename P::E* X, float (*headp)[Chain<P, WIDTH, WAVES>::M][2],
+                                  const float* bias, int l, int64_t ray0, int64_t n_act, int nt0, int lane,
+                                  int wave) {
   using C = Chain<P, WIDTH, WAVES>;
   using E = typename P::E;
   constexpr int RT = C::RT, NT = C::NT, LDX = C::LDX;
-  const float* bias = reinterpret_cast<const float*>(a.packed + a.lay.b_off) + (int64_t)l * WIDTH;
   const float* hw = reinterpret_cast<const float*>(a.packed + a.lay.head_w_off);
   const bool last = (l + 1 == a.n_hidden);
   float hp0[RT], hp1[RT], mx = 0.f;
@@ -98,6 +98,8 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
   constexpr int M = C::M, RT = C::RT, NT = C::NT, LDX = C::LDX;
   __shared__ __attribute__((aligned(16))) E X[C::XSIZE];
   __shared__ float headp[WAVES][M][2];
+  // query modes: the current layer's bias, each wave's own neurons copied in by that wave
+  __shared__ __attribute__((aligned(16))) float bsm[WIDTH];
 
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
@@ -125,6 +127,18 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
     constexpr bool kTrans = MODE != kModeTrain;
+    // query modes: fetch the bias of the wave's own neurons now (into registers, moved to LDS
+    // after the product), so that the epilogue never waits on a global load queued behind the
+    // next layer's weight blocks
+    constexpr int kNW = WIDTH / WAVES;            // neurons per wave
+    constexpr int kBL = (kNW + 63) / 64;          // bias values per lane
+    float bv[kBL];
+    if constexpr (kTrans) {
+      const float* bl = bias_all + (int64_t)l * WIDTH + nt0 * 32;
+#pragma unroll
+      for (int j = 0; j < kBL; ++j)
+        if (j * 64 + lane < kNW) bv[j] = bl[j * 64 + lane];
+    }
     // query modes issue a layer's first weight blocks before the previous layer's epilogue
     // (they do not depend on its output); the training epilogue has no registers to spare
     if (l == 0) {
@@ -134,10 +148,15 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
       if (!kTrans) C::preload(ring, W, WIDTH / P::KBLK, nt0, lane);
       C::template gemm<WIDTH / P::KBLK, kTrans>(acc, X, W, K / P::KBLK, nt0, lane, ring);
     }
+    if constexpr (kTrans) {
+#pragma unroll
+      for (int j = 0; j < kBL; ++j)
+        if (j * 64 + lane < kNW) bsm[nt0 * 32 + j * 64 + lane] = bv[j];
+    }
     if (kTrans && l + 1 < a.n_hidden) C::preload(ring, a.packed + a.lay.w_off[l + 1], WIDTH / P::KBLK, nt0, lane);
     __syncthreads();   // every wave is done reading X
     if constexpr (kTrans) {
-      epilogue_t<P, WIDTH, MODE, WAVES>(a, acc, X, headp, l, ray0, n_act, nt0, lane, wave);
+      epilogue_t<P, WIDTH, MODE, WAVES>(a, acc, X, headp, bsm, l, ray0, n_act, nt0, lane, wave);
       continue;
     }
 

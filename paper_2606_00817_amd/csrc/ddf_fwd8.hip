@@ -37,34 +37,50 @@ __device__ inline i32x8 buf_b8(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
   return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
-// Four non-negative values, already divided by the next layer's scale, as four e4m3 codes in
-// one word (element i in byte i): saturate at 448, then round to nearest even.
+// Four values in [0, 448], already divided by the next layer's scale, as four e4m3 codes in
+// one word (element i in byte i), rounded to nearest even.
 __device__ inline uint32_t pack_e4m3(float y0, float y1, float y2, float y3) {
-  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(fminf(y0, 448.f), fminf(y1, 448.f), 0, false);
-  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(fminf(y2, 448.f), fminf(y3, 448.f), lo, true);
+  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(y0, y1, 0, false);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y2, y3, lo, true);
 }
 
-// acc[rt][t] += G[rt rows][0:K1] * W1[tile (tile0 + t)][0:K1]^T   (bf16 operands)
+// acc[rt][t] += G[rt rows][0:K1] * W1[tile (tile0 + t)][0:K1]^T   (bf16 operands, 1 KiB
+// blocks).  The weight loads run two blocks ahead in a ring of three; the loads past the end
+// of the layer are bounds-checked by the buffer resource (zeros, never used).
 template <int NTP>
 __device__ inline void gemm_l1(f32x16 (&acc)[kRT8][NTP], const __bf16* G, const void* W, int KB,
                                int tile0, int lane, int width) {
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, width * KB * 32, 0x00020000);
   const int voff = lane * 16;
+  const int base = tile0 * KB * 1024, tstride = KB * 1024;
   const __bf16* xrow = G + (lane & 31) * kLDG + 8 * (lane >> 5);
-  for (int k = 0; k < KB; ++k) {
-    bf16x8 b[NTP];
+  bf16x8 b[3][NTP];
+#pragma unroll
+  for (int st = 0; st < 2; ++st)
 #pragma unroll
     for (int t = 0; t < NTP; ++t)
-      b[t] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, ((tile0 + t) * KB + k) * 1024, 0));
-    bf16x8 av[kRT8];
+      b[st][t] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, base + t * tstride + st * 1024, 0));
+  // three steps per pass of the loop keep the ring's indexing static
+  for (int k = 0; k < KB; k += 3) {
 #pragma unroll
-    for (int rt = 0; rt < kRT8; ++rt) av[rt] = *reinterpret_cast<const bf16x8*>(xrow + rt * 32 * kLDG + k * 16);
+    for (int j = 0; j < 3; ++j) {
+      if (k + j < KB) {
 #pragma unroll
-    for (int rt = 0; rt < kRT8; ++rt)
+        for (int t = 0; t < NTP; ++t)
+          b[(j + 2) % 3][t] = __builtin_bit_cast(
+              bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, base + t * tstride + (k + j + 2) * 1024, 0));
+        bf16x8 av[kRT8];
 #pragma unroll
-      for (int t = 0; t < NTP; ++t)
-        acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[t], av[rt], acc[rt][t], 0, 0, 0);
+        for (int rt = 0; rt < kRT8; ++rt)
+          av[rt] = *reinterpret_cast<const bf16x8*>(xrow + rt * 32 * kLDG + (k + j) * 16);
+#pragma unroll
+        for (int rt = 0; rt < kRT8; ++rt)
+#pragma unroll
+          for (int t = 0; t < NTP; ++t)
+            acc[rt][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b[j][t], av[rt], acc[rt][t], 0, 0, 0);
+      }
+    }
   }
 }
 
@@ -107,28 +123,50 @@ __device__ inline void gemm_f8(f32x16 (&acc)[kRT8][NTP], const uint8_t* X, const
   }
 }
 
+// Weight block (t, k) of an e4m3 layer for the streamed product below, at byte
+// ((tile0 + t) KB + k) 2 KiB + lane 32 of the layer: the per-lane part and (k mod 2) 2 KiB go
+// into the vector offset, the wave-uniform tile and k / 2 part into the scalar offset.
+template <int KB>
+__device__ inline i32x8 ld8(__amdgpu_buffer_rsrc_t rs, int voff, int base, int t, int k) {
+  return buf_b8(rs, voff + (k & 1) * 2048, base + t * KB * 2048 + (k >> 1) * 4096);
+}
+
+template <int KB>
+__device__ inline __amdgpu_buffer_rsrc_t rsrc8(const void* W, int width) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, width * KB * 64, 0x00020000);
+}
+
+// Stages of the streamed product's weight ring.
+constexpr int kS8 = 3;
+
+// First kS8 - 1 stages of an e4m3 layer's weight ring (issued ahead of time, before the
+// previous pass's epilogue: the weights do not depend on its output).
+template <int NTP, int KB>
+__device__ inline void preload8(i32x8 (&b)[kS8][NTP], const void* W, int tile0, int lane, int width) {
+  const __amdgpu_buffer_rsrc_t rs = rsrc8<KB>(W, width);
+#pragma unroll
+  for (int st = 0; st < kS8 - 1; ++st)
+#pragma unroll
+    for (int t = 0; t < NTP; ++t) b[st][t] = ld8<KB>(rs, lane * 32, tile0 * KB * 2048, t, st);
+}
+
 // The same product with the activation operand streamed one 32-ray tile at a time (the
 // next tile's LDS read overlaps the current tile's products): fewer registers, for the
-// 8-wave layout where two waves share a SIMD's register file.
+// 8-wave layout where two waves share a SIMD's register file.  The ring's first kS8 - 1
+// stages come from preload8.
 template <int NTP, int LDX, int KB>
 __device__ inline void gemm_f8_stream(f32x16 (&acc)[kRT8][NTP], const uint8_t* X, const void* W, int tile0,
-                                      int lane, int width) {
-  const __amdgpu_buffer_rsrc_t rs =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(W), (short)0, width * KB * 64, 0x00020000);
+                                      int lane, int width, i32x8 (&b)[kS8][NTP]) {
+  const __amdgpu_buffer_rsrc_t rs = rsrc8<KB>(W, width);
   const int voff = lane * 32;
   const int base = tile0 * KB * 2048;
   const uint8_t* xrow = X + (lane & 31) * LDX + 32 * (lane >> 5);
-  i32x8 b[3][NTP];
-#pragma unroll
-  for (int st = 0; st < 2; ++st)
-#pragma unroll
-    for (int t = 0; t < NTP; ++t) b[st][t] = buf_b8(rs, voff, base + (t * KB + st) * 2048);
   i32x8 av[2];
   av[0] = lds_a8(xrow);
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
 #pragma unroll
-    for (int t = 0; t < NTP; ++t) b[(k + 2) % 3][t] = buf_b8(rs, voff, base + (t * KB + k + 2) * 2048);
+    for (int t = 0; t < NTP; ++t) b[(k + kS8 - 1) % kS8][t] = ld8<KB>(rs, voff, base, t, k + kS8 - 1);
 #pragma unroll
     for (int rt = 0; rt < kRT8; ++rt) {
       const int i = k * kRT8 + rt;            // running tile index: parity picks the buffer
@@ -139,7 +177,7 @@ __device__ inline void gemm_f8_stream(f32x16 (&acc)[kRT8][NTP], const uint8_t* X
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < NTP; ++t)
-        acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(b[k % 3][t], av[i & 1], acc[rt][t], 0, 0, 0,
+        acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(b[k % kS8][t], av[i & 1], acc[rt][t], 0, 0, 0,
                                                                      127, 0, 127);
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -156,6 +194,8 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
   constexpr int XBYTES = kM8 * LDX > kM8 * kLDG * 2 ? kM8 * LDX : kM8 * kLDG * 2;
   __shared__ __attribute__((aligned(16))) uint8_t smem[XBYTES];
   __shared__ float headp[WAVES][kM8][2];
+  // the current layer's bias, each wave's own neurons copied in by that wave
+  __shared__ __attribute__((aligned(16))) float bsm[WIDTH];
   uint8_t* X = smem;
   __bf16* G = reinterpret_cast<__bf16*>(smem);
 
@@ -175,13 +215,25 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
   const float* hb = reinterpret_cast<const float*>(a.packed + a.lay.head_b_off);
   const float* scales = reinterpret_cast<const float*>(a.packed + a.lay.scale_off);
 
+  i32x8 ring[kS8][NTW / 2];                // e4m3 weight ring (8-wave layout)
   for (int l = 0; l < a.n_hidden; ++l) {
     const bool last = (l + 1 == a.n_hidden);
     const float dq = scales[4 * l + kDequant];
     const float qn = scales[4 * l + kQuantNext];
     const float dqn = dq * qn;
-    const float* bias = bias_all + (int64_t)l * WIDTH;
     const void* W = a.packed + a.lay.w_off[l];
+    // the bias of the wave's own neurons: fetched before the products, moved to LDS after
+    // the first one, so that no epilogue waits on a global load queued behind weight blocks
+    constexpr int kNW = WIDTH / WAVES;            // neurons per wave
+    constexpr int kBL = (kNW + 63) / 64;          // bias values per lane
+    float bv[kBL];
+    {
+      const float* bl = bias_all + (int64_t)l * WIDTH + wave * kNW;
+#pragma unroll
+      for (int j = 0; j < kBL; ++j)
+        if (j * 64 + lane < kNW) bv[j] = bl[j * 64 + lane];
+    }
+    const float* bias = bsm;
     // Operand roles are swapped (weights as the first matrix-core operand): register group q
     // of tile (rt, t) holds neurons (tile0 + t) 32 + 8 q + 4 (lane / 32) + i, i < 4, of ray
     // rt 32 + lane % 32, so 4 consecutive e4m3 results leave as one 32-bit LDS write.
@@ -197,14 +249,23 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
       for (int rt = 0; rt < kRT8; ++rt)
 #pragma unroll
         for (int t = 0; t < NTP; ++t) acc[rt][t] = f32x16{};
-      if (l == 0)
+      if (l == 0) {
         gemm_l1<NTP>(acc, G, W, a.lay.k1 / 16, tile0, lane, WIDTH);
-      else
-      {
-        if constexpr (WAVES == 8)
-          gemm_f8_stream<NTP, LDX, WIDTH / 64>(acc, X, W, tile0, lane, WIDTH);
-        else
-          gemm_f8<NTP, LDX, WIDTH / 64>(acc, X, W, tile0, lane, WIDTH);
+      } else if constexpr (WAVES == 8) {
+        // pass 0 finds its first weight blocks already issued (end of the previous layer)
+        if (p == 1) preload8<NTP, WIDTH / 64>(ring, W, tile0, lane, WIDTH);
+        gemm_f8_stream<NTP, LDX, WIDTH / 64>(acc, X, W, tile0, lane, WIDTH, ring);
+      } else {
+        gemm_f8<NTP, LDX, WIDTH / 64>(acc, X, W, tile0, lane, WIDTH);
+      }
+      // the next layer's first weight blocks do not depend on this layer's output: issue them
+      // before the epilogue (after the last layer, a harmless re-read of its own blocks)
+      if (WAVES == 8 && p == 1)
+        preload8<NTP, WIDTH / 64>(ring, a.packed + a.lay.w_off[last ? l : l + 1], wave * NTW, lane, WIDTH);
+      if (p == 0) {
+#pragma unroll
+        for (int j = 0; j < kBL; ++j)
+          if (j * 64 + lane < kNW) bsm[wave * kNW + j * 64 + lane] = bv[j];
       }
       if (p == 1) __syncthreads();   // every wave is done reading this layer's input
       // the two epilogues are separate uniform branches, so that neither carries the
@@ -259,7 +320,8 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
             for (int rt = 0; rt < kRT8; ++rt) {
               float y[4];
 #pragma unroll
-              for (int i = 0; i < 4; ++i) y[i] = fmaxf(fmaf(acc[rt][t][4 * q + i], dqn, bq[i]), 0.f);
+              for (int i = 0; i < 4; ++i)   // ReLU and saturation at 448 in one clamp
+                y[i] = __builtin_amdgcn_fmed3f(fmaf(acc[rt][t][4 * q + i], dqn, bq[i]), 0.f, 448.f);
               const uint32_t w = pack_e4m3(y[0], y[1], y[2], y[3]);
               if (p == 0)
                 hold[rt][t][q] = w;
