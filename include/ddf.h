@@ -117,23 +117,34 @@ typedef struct {
   float bce_weight;    /* weight of the hit cross-entropy, 0.3 (Sec. III-D) */
   float l1_clamp;      /* clamp of the per-ray L1 distance error, e.g. 3.0 (box scale) */
   int64_t step;        /* 1-based Adam step count (bias correction) */
+  int32_t recompute_every; /* activation recomputation span k (see below); 0 = keep all */
 } ddf_train_hparams;
 
+/* Activation recomputation (the deep-net training mode): with recompute_every = k,
+ * 0 < k < n_hidden, the training forward keeps only the encoded features and the
+ * checkpoints H_k, H_2k, .., H_n; the backward pass walks the layers in segments from the
+ * top and reruns each segment's forward from the checkpoint below it (bit-identical to the
+ * first pass) before its deltas and weight gradients.  Costs up to one extra forward pass;
+ * keeps ceil(n/k) + k - 1 activation slabs and k + 1 delta slabs instead of n and n.
+ * k = 0 or k >= n_hidden keeps every activation.  Negative k is DDF_ERR_INVALID_ARG.
+ * The same k must be used for the workspace size, the forward and the backward call. */
+
 /* Workspace for one training step / backward pass over `batch` rays. */
-size_t ddf_train_workspace_bytes(const ddf_net_desc* desc, int64_t batch);
+size_t ddf_train_workspace_bytes(const ddf_net_desc* desc, int64_t batch, int32_t recompute_every);
 
 /* Training-mode forward: z_t and z_xi logits per ray [n], and the activations the
  * backward pass needs kept in `ws`.  Same numerics as ddf_query. */
 int ddf_forward_train(const ddf_net_desc* desc, const void* packed, const float* rays,
-                      int64_t n, float* z_t, float* z_xi, void* ws, size_t ws_bytes,
-                      void* stream);
+                      int64_t n, float* z_t, float* z_xi, int32_t recompute_every, void* ws,
+                      size_t ws_bytes, void* stream);
 
 /* Backward pass of the network for given logit gradients (dL/dz_t, dL/dz_xi), each
- * device float32 [n]; must follow ddf_forward_train on the same rays and ws.  Writes the
- * float32 gradient of every parameter (master layout) to grad_params (device). */
+ * device float32 [n]; must follow ddf_forward_train on the same rays, recompute_every and
+ * ws (rays are read again when the first segment is recomputed).  Writes the float32
+ * gradient of every parameter (master layout) to grad_params (device). */
 int ddf_backward(const ddf_net_desc* desc, const void* packed, const float* rays, int64_t n,
                  const float* grad_z_t, const float* grad_z_xi, float* grad_params,
-                 void* ws, size_t ws_bytes, void* stream);
+                 int32_t recompute_every, void* ws, size_t ws_bytes, void* stream);
 
 /* One distillation step (Sec. III-B, III-D): forward, loss, backward, Adam, repack.
  *   loss = mean over hit rays of min(|softplus(z_t) - t_gt|, l1_clamp)
@@ -146,7 +157,8 @@ int ddf_backward(const ddf_net_desc* desc, const void* packed, const float* rays
  *   loss_out                 device float32 [3]: total, l1 term, bce term.
  *   nonfinite_flag           device int32 [1]: set to 1 and the update skipped (master,
  *                            m, v untouched) when any gradient is not finite, else 0.
- *   grad_out                 device float32 [ddf_param_count] or NULL: the gradient. */
+ *   grad_out                 device float32 [ddf_param_count] or NULL: the gradient.
+ *   ws                       ddf_train_workspace_bytes(desc, batch, hp->recompute_every). */
 int ddf_train_step(const ddf_net_desc* desc, float* master, float* adam_m, float* adam_v,
                    void* packed, const float* rays, const float* t_gt, const uint8_t* hit_gt,
                    int64_t batch, const ddf_train_hparams* hp, float* loss_out,
@@ -191,7 +203,7 @@ int ddf_scene_sdf(const float* prims, int32_t n_prims, const float* points, int6
  *   loss = mean over points of |s(p) - sdf_gt(p)|
  * with the same forward, backward, Adam and repack as ddf_train_step (hp->bce_weight and
  * hp->l1_clamp are ignored).  points [3][n], sdf_gt [n]; loss_out device float32 [3]
- * (loss, loss, 0); workspace ddf_train_workspace_bytes(desc, n). */
+ * (loss, loss, 0); workspace ddf_train_workspace_bytes(desc, n, hp->recompute_every). */
 int sdf_train_step(const ddf_net_desc* desc, float* master, float* adam_m, float* adam_v, void* packed,
                    const float* points, const float* sdf_gt, int64_t n, const ddf_train_hparams* hp,
                    float* loss_out, int32_t* nonfinite_flag, float* grad_out, void* ws, size_t ws_bytes,

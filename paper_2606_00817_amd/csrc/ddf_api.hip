@@ -63,6 +63,7 @@ FwdArgs base_args(const ddf_net_desc& d, const void* packed) {
   a.packed = static_cast<const uint8_t*>(packed);
   a.lay = make_layout(d);
   a.n_in = d.n_in; a.n_freq = d.n_freq; a.n_hidden = d.n_hidden; a.n_out = d.n_out;
+  a.l_begin = 0; a.l_end = d.n_hidden;
   return a;
 }
 

@@ -10,7 +10,8 @@ enum FwdMode {
   kModeTrain = 1,   // raw logits + activations kept for the backward pass
   kModeSdf = 2,     // signed distance z_0 at points
   kModeTrace = 3,   // one sphere-tracing step over the active-ray list
-  kModeCalib = 4    // query that records max h_l of hidden layers 1..n-1 (FP8 scales)
+  kModeCalib = 4,   // query that records max h_l of hidden layers 1..n-1 (FP8 scales)
+  kModeRecompute = 5  // training: rerun hidden layers from a kept activation, keeping theirs
 };
 
 struct FwdArgs {
@@ -23,9 +24,13 @@ struct FwdArgs {
   int mode;
   float* out0;            // query: t; train: z_t; sdf: s
   float* out1;            // query: xi; train: z_xi
-  // train mode: activation store, slabs of `act_rows` rows in [rows / 8][cols][8] layout:
-  // the encoded features (k1_half columns) then H_1 .. H_n (width columns each).
-  void* act;
+  // 0-based hidden layers this launch runs: [l_begin, l_end) (queries: all of them)
+  int l_begin, l_end;
+  // train / recompute modes: activation stores of `act_rows` rows, [rows / 8][cols][8]
+  // layout: hst[0] the encoded features (k1_half columns), hst[l] H_l, the output of
+  // hidden layer l (1-based, width columns); a null entry is not kept.  The recompute
+  // mode reads its input tile from hst[l_begin].
+  void* hst[kMaxLayers + 1];
   int64_t act_rows;
   // trace mode
   const int32_t* idx;     // active rays of this step
@@ -57,8 +62,8 @@ __device__ inline void trace_update(const FwdArgs& a, int32_t src, float s) {
 
 // Encoded inputs of rays [ray0, ray0 + M) into X[:, 0:k1]; padding columns are zero.
 // Reduced precisions store the bf16 hi part in columns [0, k1_half) and the lo part
-// in [k1_half, k1).  Train mode also writes the features (fp32, or bf16 hi) to slab 0
-// of the activation store, layout [rows / 8][k1_half][8].
+// in [k1_half, k1).  Train mode also writes the features (fp32, or bf16 hi) to the
+// feature store hst[0] when there is one, layout [rows / 8][k1_half][8].
 template <class E, int M, int LDX, int MODE>
 __device__ void encode_tile(const FwdArgs& a, int64_t ray0, E* X) {
   const int n_in = a.n_in, nf = a.n_freq;
@@ -102,8 +107,8 @@ __device__ void encode_tile(const FwdArgs& a, int64_t ray0, E* X) {
       } else {
         X[r * LDX + c] = (E)f;
       }
-      if (MODE == kModeTrain)
-        reinterpret_cast<E*>(a.act)[((g >> 3) * khalf + c) * 8 + (g & 7)] = (E)f;
+      if (MODE == kModeTrain && a.hst[0])
+        reinterpret_cast<E*>(a.hst[0])[((g >> 3) * khalf + c) * 8 + (g & 7)] = (E)f;
     }
   }
   const int pad = khalf - a.lay.n_feat;
@@ -111,13 +116,25 @@ __device__ void encode_tile(const FwdArgs& a, int64_t ray0, E* X) {
     const int r = idx % M, c = a.lay.n_feat + idx / M;
     X[r * LDX + c] = (E)0.f;
     if (split) X[r * LDX + khalf + c] = (E)0.f;
-    if (MODE == kModeTrain) {
+    if (MODE == kModeTrain && a.hst[0]) {
       const int64_t g = ray0 + r;
-      reinterpret_cast<E*>(a.act)[((g >> 3) * khalf + c) * 8 + (g & 7)] = (E)0.f;
+      reinterpret_cast<E*>(a.hst[0])[((g >> 3) * khalf + c) * 8 + (g & 7)] = (E)0.f;
     }
   }
 }
 
+// Recompute mode: the kept activation H_(l_begin) of rays [ray0, ray0 + M) into X[:, 0:W]
+// (exactly the operand tile the forward pass had in LDS).
+template <class E, int M, int LDX, int WIDTH>
+__device__ void load_tile(const FwdArgs& a, int64_t ray0, E* X) {
+  const E* H = reinterpret_cast<const E*>(a.hst[a.l_begin]);
+  for (int idx = threadIdx.x; idx < M * WIDTH; idx += blockDim.x) {
+    const int q = idx & 7;
+    const int c = (idx >> 3) % WIDTH;
+    const int rb = (idx >> 3) / WIDTH;
+    X[(rb * 8 + q) * LDX + c] = H[(((ray0 >> 3) + rb) * WIDTH + c) * 8 + q];
+  }
+}
 
 hipError_t launch_forward(const ddf_net_desc& d, const FwdArgs& a, int64_t n_items,
                           hipStream_t st);

@@ -109,7 +109,10 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
   FwdArgs aa = a;
   aa.n = n_act;
 
-  encode_tile<E, M, LDX, MODE>(aa, ray0, X);
+  if constexpr (MODE == kModeRecompute)
+    load_tile<E, M, LDX, WIDTH>(a, ray0, X);
+  else
+    encode_tile<E, M, LDX, MODE>(aa, ray0, X);
   __syncthreads();
 
   const float* bias_all = reinterpret_cast<const float*>(a.packed + a.lay.b_off);
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
   const int nt0 = wave * NT;
   typename C::Ring ring;
 
-  for (int l = 0; l < a.n_hidden; ++l) {
+  for (int l = a.l_begin; l < a.l_end; ++l) {
     const int K = l == 0 ? a.lay.k1 : WIDTH;
     const void* W = a.packed + a.lay.w_off[l];
     f32x16 acc[RT][NT];
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
-    constexpr bool kTrans = MODE != kModeTrain;
+    constexpr bool kTrans = MODE != kModeTrain && MODE != kModeRecompute;
     // query modes: fetch the bias of the wave's own neurons now (into registers, moved to LDS
     // after the product), so that the epilogue never waits on a global load queued behind the
     // next layer's weight blocks
@@ -153,7 +156,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
       for (int j = 0; j < kBL; ++j)
         if (j * 64 + lane < kNW) bsm[nt0 * 32 + j * 64 + lane] = bv[j];
     }
-    if (kTrans && l + 1 < a.n_hidden) C::preload(ring, a.packed + a.lay.w_off[l + 1], WIDTH / P::KBLK, nt0, lane);
+    if (kTrans && l + 1 < a.l_end) C::preload(ring, a.packed + a.lay.w_off[l + 1], WIDTH / P::KBLK, nt0, lane);
     __syncthreads();   // every wave is done reading X
     if constexpr (kTrans) {
       epilogue_t<P, WIDTH, MODE, WAVES>(a, acc, X, headp, bsm, l, ray0, n_act, nt0, lane, wave);
@@ -162,10 +165,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
 
     const float* bias = bias_all + (int64_t)l * WIDTH;
     const bool last = (l + 1 == a.n_hidden);
-    E* slab = MODE == kModeTrain
-                  ? reinterpret_cast<E*>(a.act) + (int64_t)a.lay.k1_half * a.act_rows +
-                        (int64_t)l * WIDTH * a.act_rows
-                  : nullptr;
+    E* slab = reinterpret_cast<E*>(a.hst[l + 1]);   // H_(l+1) store, or null: not kept
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       float hp0[16], hp1[16];
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
             if (lane == 0) atomicMax(a.amax + l, __float_as_uint(m));
           }
         }
-        if (MODE == kModeTrain) {
+        if (slab) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int64_t g0 = ray0 + rt * 32 + 8 * q;   // 8-ray block of registers 4q..4q+3
@@ -228,6 +228,8 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
     __syncthreads();
   }
 
+  // a recomputation (a layer range short of the heads) has the kept activations as output
+  if (MODE == kModeRecompute || a.l_end != a.n_hidden) return;
   for (int r = threadIdx.x; r < M; r += WAVES * 64) {
     const int64_t g = ray0 + r;
     if (g >= n_act) continue;
@@ -266,6 +268,9 @@ static hipError_t launch_t(const FwdArgs& a, int64_t n_tiles, hipStream_t st) {
     case kModeTrain: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrain, QW>), grid, bq, 0, st, a); break;
     case kModeSdf: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeSdf, QW>), grid, bq, 0, st, a); break;
     case kModeCalib: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeCalib, QW>), grid, bq, 0, st, a); break;
+    case kModeRecompute:
+      hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeRecompute, QW>), grid, bq, 0, st, a);
+      break;
     default: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrace, QW>), grid, bq, 0, st, a); break;
   }
   return hipGetLastError();

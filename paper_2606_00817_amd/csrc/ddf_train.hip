@@ -1,12 +1,17 @@
 // Training path of libddf: forward with kept activations, distillation loss,
 // backward through the fused chain, weight gradients, Adam on the fp32 master.
 //
-// Workspace (one training batch of n rays, rows padded to R = n rounded up to 128):
-//   act    [k1_half + n_hidden * width] columns x R rows, [R / 8][cols][8] layout
-//          per slab: the encoded features, then H_1 .. H_n (post-ReLU), operand type
-//   delta  n_hidden slabs [R / 8][width][8]: dL/da_l of every hidden layer
+// Workspace (one training batch of n rays, rows padded to R = n rounded up to 128; every
+// store below is [R / 8][cols][8], in the operand type):
+//   feat   the encoded features (k1_half columns)
+//   hkeep  the kept hidden activations (width columns each): all of H_1 .. H_n, or with
+//          activation recomputation every k layers only the checkpoints H_k, H_2k, .., H_n
+//   hseg   (recomputation) k - 1 slabs for the recomputed layers of one segment
+//   delta  dL/da_l: n slabs, or (recomputation) a ring of k + 1
 //   z_t, z_xi, dz_t, dz_xi   fp32 [R] each
 //   loss partials, scalars, and (when the caller passes none) the gradient buffer.
+// Rows n .. R - 1 are computed from zero inputs with zero logit gradients, so they add
+// nothing to any sum.
 // Everything is deterministic: no floating-point atomics; every reduction has a
 // fixed order.
 #include "ddf_chain.h"
@@ -20,7 +25,8 @@ constexpr int kHeadChunks = 64;   // ray chunks of the head-gradient reduction
 
 struct TrainWs {
   int64_t R;                // padded rows
-  int64_t act, delta;       // byte offsets of the two stores
+  int rc;                   // recomputation span k (0: every activation kept)
+  int64_t feat, hkeep, hseg, delta;   // byte offsets of the stores
   int64_t zt, zx, dzt, dzx; // fp32 [R]
   int64_t lossp;            // [kLossBlocks][8] floats
   int64_t scal;             // 64 bytes of scalars
@@ -31,14 +37,25 @@ struct TrainWs {
   int esize;
 };
 
-inline TrainWs train_ws(const ddf_net_desc& d, int64_t batch, size_t nparams) {
+// The recomputation span actually used: none when it would not save anything.
+inline int recompute_span(const ddf_net_desc& d, int recompute_every) {
+  return recompute_every > 0 && recompute_every < d.n_hidden ? recompute_every : 0;
+}
+
+inline TrainWs train_ws(const ddf_net_desc& d, int64_t batch, size_t nparams, int recompute_every) {
   const Layout L = make_layout(d);
   TrainWs w{};
   w.esize = d.precision == DDF_FP32 ? 4 : 2;
   w.R = (batch + 127) / 128 * 128;
+  w.rc = recompute_span(d, recompute_every);
+  const int n = d.n_hidden;
+  const int kept = w.rc ? (n + w.rc - 1) / w.rc : n;
+  const int64_t S = (int64_t)d.width * w.R * w.esize;
   int64_t off = 0;
-  w.act = off; off = align256(off + ((int64_t)L.k1_half + (int64_t)d.n_hidden * d.width) * w.R * w.esize);
-  w.delta = off; off = align256(off + (int64_t)d.n_hidden * d.width * w.R * w.esize);
+  w.feat = off; off = align256(off + (int64_t)L.k1_half * w.R * w.esize);
+  w.hkeep = off; off = align256(off + kept * S);
+  w.hseg = off; off = align256(off + (w.rc ? w.rc - 1 : 0) * S);
+  w.delta = off; off = align256(off + (w.rc ? w.rc + 1 : n) * S);
   w.zt = off; off = align256(off + 4 * w.R);
   w.zx = off; off = align256(off + 4 * w.R);
   w.dzt = off; off = align256(off + 4 * w.R);
@@ -50,6 +67,36 @@ inline TrainWs train_ws(const ddf_net_desc& d, int64_t batch, size_t nparams) {
   w.dwpart = off; off = align256(off + 32 * (int64_t)nparams);
   w.total = off;
   return w;
+}
+
+// Where each activation and delta lives.  h[0] the features, h[l] H_l (1-based); with
+// recomputation H_l of a checkpoint (l a multiple of k, or l = n) has its own kept slab and
+// the others share the segment slabs, slot (l - 1) mod k; delta_l sits in ring slot
+// l mod (k + 1), so a segment's deltas and the one above it never collide.
+struct TrainPtrs {
+  uint8_t* h[kMaxLayers + 1];
+  uint8_t* dl[kMaxLayers + 1];
+  bool kept[kMaxLayers + 1];   // written by the training forward pass
+};
+
+inline TrainPtrs train_ptrs(const ddf_net_desc& d, const TrainWs& w, uint8_t* ws) {
+  TrainPtrs p{};
+  const int n = d.n_hidden;
+  const int64_t S = (int64_t)d.width * w.R * w.esize;
+  p.h[0] = ws + w.feat;
+  p.kept[0] = true;
+  for (int l = 1; l <= n; ++l) {
+    if (w.rc == 0) {
+      p.h[l] = ws + w.hkeep + (l - 1) * S;
+      p.kept[l] = true;
+      p.dl[l] = ws + w.delta + (l - 1) * S;
+    } else {
+      p.kept[l] = l % w.rc == 0 || l == n;
+      p.h[l] = p.kept[l] ? ws + w.hkeep + (int64_t)((l - 1) / w.rc) * S : ws + w.hseg + (int64_t)((l - 1) % w.rc) * S;
+      p.dl[l] = ws + w.delta + (int64_t)(l % (w.rc + 1)) * S;
+    }
+  }
+  return p;
 }
 
 // Float offsets of every layer's weight and bias in the master vector.
@@ -212,15 +259,17 @@ struct BwdArgs {
   Layout lay;
   int n_hidden, n_out;
   int64_t R;
-  const void* act;
-  void* delta;
+  const void* h[kMaxLayers + 1];   // H_l stores (1-based; the masks)
+  void* dl[kMaxLayers + 1];        // delta_l stores
+  int lo, hi;                      // this launch computes delta_hi .. delta_lo (1-based)
   const float* dzt;
   const float* dzx;
 };
 
-// delta_n = (dz_t w_t + dz_xi w_xi) * 1[H_n > 0]; then for l = n..2:
-// delta_(l-1) = (delta_l W_l) * 1[H_(l-1) > 0], the product on the matrix cores with the
-// transposed weight blocks, the running delta resident in LDS.  Every delta_l is stored.
+// delta_n = (dz_t w_t + dz_xi w_xi) * 1[H_n > 0]; delta_(l) = (delta_(l+1) W_(l+1)) *
+// 1[H_l > 0], the product on the matrix cores with the transposed weight blocks, the running
+// delta resident in LDS.  One launch covers layers hi down to lo: from the logit gradients
+// when hi = n, else from the stored delta_(hi+1).  Every delta it computes is stored.
 template <class P, int WIDTH, int WAVES>
 __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
   using C = Chain<P, WIDTH, WAVES>;
@@ -230,15 +279,12 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t ray0 = (int64_t)blockIdx.x * M;
-  const E* act = reinterpret_cast<const E*>(a.act);
-  E* delta = reinterpret_cast<E*>(a.delta);
-  const int64_t slab = (int64_t)WIDTH * a.R;
-  const E* H = act + (int64_t)a.lay.k1_half * a.R;      // H_1 slab; H_l at (l - 1) * slab
   const float* hw = reinterpret_cast<const float*>(a.packed + a.lay.head_w_off);
 
-  {
-    const E* Hn = H + (int64_t)(a.n_hidden - 1) * slab;
-    E* Dn = delta + (int64_t)(a.n_hidden - 1) * slab;
+  int top;   // the first delta the loop computes
+  if (a.hi == a.n_hidden) {
+    const E* Hn = reinterpret_cast<const E*>(a.h[a.n_hidden]);
+    E* Dn = reinterpret_cast<E*>(a.dl[a.n_hidden]);
     for (int idx = threadIdx.x; idx < M * WIDTH; idx += WAVES * 64) {
       const int q = idx & 7;
       const int j = (idx >> 3) % WIDTH;
@@ -251,22 +297,32 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
       X[(rb * 8 + q) * LDX + j] = (E)d;
       Dn[gi] = (E)d;
     }
+    top = a.n_hidden - 1;
+  } else {
+    const E* Du = reinterpret_cast<const E*>(a.dl[a.hi + 1]);
+    for (int idx = threadIdx.x; idx < M * WIDTH; idx += WAVES * 64) {
+      const int q = idx & 7;
+      const int c = (idx >> 3) % WIDTH;
+      const int rb = (idx >> 3) / WIDTH;
+      X[(rb * 8 + q) * LDX + c] = Du[(((ray0 >> 3) + rb) * WIDTH + c) * 8 + q];
+    }
+    top = a.hi;
   }
   const int nt0 = wave * NT;
   typename C::Ring ring;
-  if (a.n_hidden > 1) C::preload(ring, a.packed + a.lay.wt_off[a.n_hidden - 1], WIDTH / P::KBLK, nt0, lane);
+  if (top >= a.lo) C::preload(ring, a.packed + a.lay.wt_off[top], WIDTH / P::KBLK, nt0, lane);
   __syncthreads();
-  for (int l = a.n_hidden - 1; l >= 1; --l) {
+  for (int l = top; l >= a.lo; --l) {
     f32x16 acc[RT][NT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
     C::template gemm<WIDTH / P::KBLK>(acc, X, a.packed + a.lay.wt_off[l], WIDTH / P::KBLK, nt0, lane, ring);
-    if (l > 1) C::preload(ring, a.packed + a.lay.wt_off[l - 1], WIDTH / P::KBLK, nt0, lane);
+    if (l > a.lo) C::preload(ring, a.packed + a.lay.wt_off[l - 1], WIDTH / P::KBLK, nt0, lane);
     __syncthreads();
-    const E* Hm = H + (int64_t)(l - 1) * slab;        // H_(l-1): output of hidden layer l - 1
-    E* Dm = delta + (int64_t)(l - 1) * slab;
+    const E* Hm = reinterpret_cast<const E*>(a.h[l]);   // H_l: the mask of delta_l
+    E* Dm = reinterpret_cast<E*>(a.dl[l]);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int n = (nt0 + t) * 32 + (lane & 31);
@@ -302,20 +358,22 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
 // ------------------------------------------------------------------ weight gradients
 
 struct DwArgs {
-  const uint8_t* act;     // features slab then H_1..H_n
-  const uint8_t* delta;   // delta_1..delta_n
+  const uint8_t* h[kMaxLayers + 1];    // layer inputs: h[0] the features, h[l] H_l
+  const uint8_t* dl[kMaxLayers + 1];   // delta_l stores (1-based)
   float* grad;            // final gradient (one split) or the partials [splits][P]
   MasterOffsets mo;
   int64_t R;              // padded rows
   int64_t P;              // parameters (stride of the partials)
-  int n_hidden, width, k1_half, n_feat;
-  int tiles_l0, tiles_l;  // workgroups for layer 1 and for every other hidden layer
+  int first_sq;           // 0-based index of the first square layer of this launch
+  int width, k1_half, n_feat;
+  int tiles_l0, tiles_l;  // workgroups for layer 1 (0 when it is not in this launch) and
+                          // for every other hidden layer
   int tn_l0, tn_l;        // column tiles of layer 1 / of the other layers
   int splits;             // ray ranges (blockIdx.y), each summed separately
 };
 
 // dW_l = sum_rays delta_l^T H_(l-1) (H_0 = the encoded features) and db_l = sum_rays delta_l,
-// for every hidden layer in one launch.  A workgroup owns a TM x TN tile of one layer's
+// for a run of consecutive hidden layers in one launch (all of them without recomputation).  A workgroup owns a TM x TN tile of one layer's
 // gradient over one of `splits` equal ray ranges: 4 waves in 2 x 2, each (TM/2) x (TN/2),
 // operands read in matrix-core order straight from the [R / 8][cols][8] stores through
 // buffer resources, three steps ahead in a ring of four.  Each (tile, range) sum has one
@@ -335,7 +393,7 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
     tm = blk / a.tn_l0; tn = blk % a.tn_l0;
   } else {
     blk -= a.tiles_l0;
-    layer = 1 + blk / a.tiles_l; blk %= a.tiles_l;
+    layer = a.first_sq + blk / a.tiles_l; blk %= a.tiles_l;
     cols = a.width;
     tm = blk / a.tn_l; tn = blk % a.tn_l;
   }
@@ -343,8 +401,8 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
   const int row0 = tm * TM + (wave >> 1) * (TM / 2);
   const int col0 = tn * TN + (wave & 1) * (TN / 2);
   constexpr int es = sizeof(typename P::E);
-  const uint8_t* D = a.delta + (int64_t)layer * W * a.R * es;
-  const uint8_t* Hb = layer == 0 ? a.act : a.act + ((int64_t)a.k1_half + (int64_t)(layer - 1) * W) * a.R * es;
+  const uint8_t* D = a.dl[layer + 1];   // 0-based layer `layer` is hidden layer layer + 1
+  const uint8_t* Hb = a.h[layer];
   const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(D), (short)0,
                                                                       (int)(W * a.R * es), 0x00020000);
   const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(Hb), (short)0,
@@ -622,14 +680,17 @@ static int dw_splits(int tiles, int64_t steps) {
   return s;
 }
 
+// Weight gradients of the 0-based hidden layers lo0 .. hi0 in one launch.
 template <class P>
-static hipError_t launch_dw(const ddf_net_desc& d, DwArgs& a, hipStream_t st) {
+static hipError_t launch_dw(const ddf_net_desc& d, DwArgs& a, int lo0, int hi0, hipStream_t st) {
   const int T = d.width >= 512 ? 256 : 128;   // square tiles
   a.tn_l0 = (a.k1_half + T - 1) / T;
   a.tn_l = d.width / T;
-  a.tiles_l0 = (d.width / T) * a.tn_l0;
+  a.tiles_l0 = lo0 == 0 ? (d.width / T) * a.tn_l0 : 0;
   a.tiles_l = (d.width / T) * a.tn_l;
-  const int tiles = a.tiles_l0 + (d.n_hidden - 1) * a.tiles_l;
+  a.first_sq = lo0 == 0 ? 1 : lo0;
+  const int tiles = a.tiles_l0 + (hi0 - a.first_sq + 1) * a.tiles_l;
+  if (tiles <= 0) return hipSuccess;
   const dim3 grid((unsigned)tiles, (unsigned)a.splits);
   if (T == 256)
     hipLaunchKernelGGL((dw_kernel<P, 256, 256>), grid, dim3(kThreads), 0, st, a);
@@ -638,62 +699,103 @@ static hipError_t launch_dw(const ddf_net_desc& d, DwArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-static int dw_tiles(const ddf_net_desc& d, int k1_half) {
+static int dw_tiles(const ddf_net_desc& d, int k1_half, int lo0, int hi0) {
   const int T = d.width >= 512 ? 256 : 128;
-  return (d.width / T) * ((k1_half + T - 1) / T) + (d.n_hidden - 1) * (d.width / T) * (d.width / T);
+  const int first_sq = lo0 == 0 ? 1 : lo0;
+  return (lo0 == 0 ? (d.width / T) * ((k1_half + T - 1) / T) : 0) + (hi0 - first_sq + 1) * (d.width / T) * (d.width / T);
 }
 
-// Backward from the logit gradients already in ws (dz_t, dz_xi) into grad.
-static int run_backward(const ddf_net_desc& d, const void* packed, const TrainWs& w, uint8_t* ws, float* grad,
-                        hipStream_t st) {
+// The training forward over all R rows (rows >= n from zero inputs).  Layers [0, n_hidden):
+// the logits and the kept activations (features, every H_l or the checkpoints).  A shorter
+// range [l_begin, l_end) is the recomputation of one segment's activations: from the inputs
+// when l_begin = 0, else from the kept H_(l_begin); no logits.
+static int run_forward_rows(const ddf_net_desc& d, const void* packed, const float* in, int64_t n, float* zt,
+                            float* zx, const TrainWs& w, const TrainPtrs& p, int l_begin, int l_end,
+                            hipStream_t st) {
+  FwdArgs a{};
+  a.packed = static_cast<const uint8_t*>(packed);
+  a.lay = make_layout(d);
+  a.n_in = d.n_in; a.n_freq = d.n_freq; a.n_hidden = d.n_hidden; a.n_out = d.n_out;
+  a.in = in; a.n = n; a.stride = n;
+  a.mode = l_begin == 0 ? kModeTrain : kModeRecompute;
+  a.out0 = zt; a.out1 = zx;
+  a.l_begin = l_begin; a.l_end = l_end;
+  a.act_rows = w.R;
+  const bool full = l_begin == 0 && l_end == d.n_hidden;
+  a.hst[0] = full ? p.h[0] : nullptr;
+  for (int l = 1; l <= d.n_hidden; ++l)
+    a.hst[l] = full ? (p.kept[l] ? p.h[l] : nullptr) : (l > l_begin && l <= l_end ? p.h[l] : nullptr);
+  if (l_begin > 0) a.hst[l_begin] = p.h[l_begin];   // the recomputation's input
+  return hip_status(launch_forward(d, a, w.R, st), "training forward launch");
+}
+
+// Backward from the logit gradients already in ws (dz_t, dz_xi) into grad: segment by
+// segment from the top (one segment of all layers without recomputation), each one
+// recomputing its activations from the checkpoint below it, then its delta chain, then its
+// weight gradients.
+static int run_backward(const ddf_net_desc& d, const void* packed, const float* in, int64_t n, const TrainWs& w,
+                        uint8_t* ws, float* grad, hipStream_t st) {
   const Layout L = make_layout(d);
-  BwdArgs b{};
-  b.packed = static_cast<const uint8_t*>(packed);
-  b.lay = L;
-  b.n_hidden = d.n_hidden; b.n_out = d.n_out; b.R = w.R;
-  b.act = ws + w.act; b.delta = ws + w.delta;
-  b.dzt = reinterpret_cast<const float*>(ws + w.dzt);
-  b.dzx = reinterpret_cast<const float*>(ws + w.dzx);
-  hipError_t e = d.precision == DDF_FP32 ? launch_bwd<PF32>(d, b, st) : launch_bwd<PBF16>(d, b, st);
-  if (e != hipSuccess) return hip_status(e, "backward chain launch");
-  DwArgs a{};
-  a.act = ws + w.act; a.delta = ws + w.delta;
-  a.mo = master_offsets(d);
-  a.R = w.R; a.P = (int64_t)param_count_of(d);
-  a.n_hidden = d.n_hidden; a.width = d.width; a.k1_half = L.k1_half; a.n_feat = L.n_feat;
-  a.splits = dw_splits(dw_tiles(d, L.k1_half), w.R / (d.precision == DDF_FP32 ? 8 : 16));
-  a.grad = a.splits > 1 ? reinterpret_cast<float*>(ws + w.dwpart) : grad;
-  e = d.precision == DDF_FP32 ? launch_dw<PF32>(d, a, st) : launch_dw<PBF16>(d, a, st);
-  if (e != hipSuccess) return hip_status(e, "weight-gradient launch");
-  if (a.splits > 1) {
-    sum_splits_kernel<<<2048, 256, 0, st>>>(a.grad, a.splits, a.P, a.mo.w[d.n_hidden], grad);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_status(e, "weight-gradient sum launch");
-  }
-  const int64_t hslab = ((int64_t)L.k1_half + (int64_t)(d.n_hidden - 1) * d.width) * w.R * w.esize;
-  const dim3 hb((unsigned)(d.width / 32 + 1), kHeadChunks);
+  const TrainPtrs p = train_ptrs(d, w, ws);
   const MasterOffsets mo = master_offsets(d);
+  const int nh = d.n_hidden;
+  const float* dzt = reinterpret_cast<const float*>(ws + w.dzt);
+  const float* dzx = reinterpret_cast<const float*>(ws + w.dzx);
+  hipError_t e;
+  int rc;
+  for (int hi = nh; hi >= 1;) {
+    const int lo = w.rc ? (hi - 1) / w.rc * w.rc + 1 : 1;
+    if (w.rc && hi - 1 >= lo && (rc = run_forward_rows(d, packed, in, n, nullptr, nullptr, w, p, lo - 1, hi - 1, st)))
+      return rc;
+    BwdArgs b{};
+    b.packed = static_cast<const uint8_t*>(packed);
+    b.lay = L;
+    b.n_hidden = nh; b.n_out = d.n_out; b.R = w.R;
+    for (int l = 0; l <= nh; ++l) { b.h[l] = p.h[l]; b.dl[l] = p.dl[l]; }
+    b.lo = lo; b.hi = hi;
+    b.dzt = dzt; b.dzx = dzx;
+    e = d.precision == DDF_FP32 ? launch_bwd<PF32>(d, b, st) : launch_bwd<PBF16>(d, b, st);
+    if (e != hipSuccess) return hip_status(e, "backward chain launch");
+    DwArgs a{};
+    for (int l = 0; l <= nh; ++l) { a.h[l] = p.h[l]; a.dl[l] = p.dl[l]; }
+    a.mo = mo;
+    a.R = w.R; a.P = (int64_t)param_count_of(d);
+    a.width = d.width; a.k1_half = L.k1_half; a.n_feat = L.n_feat;
+    // the ray ranges follow from the whole network, so that every tile's sum has the same
+    // order with and without recomputation (bit-identical gradients)
+    a.splits = dw_splits(dw_tiles(d, L.k1_half, 0, nh - 1), w.R / (d.precision == DDF_FP32 ? 8 : 16));
+    a.grad = a.splits > 1 ? reinterpret_cast<float*>(ws + w.dwpart) : grad;
+    e = d.precision == DDF_FP32 ? launch_dw<PF32>(d, a, lo - 1, hi - 1, st) : launch_dw<PBF16>(d, a, lo - 1, hi - 1, st);
+    if (e != hipSuccess) return hip_status(e, "weight-gradient launch");
+    if (a.splits > 1) {
+      const int64_t o0 = mo.w[lo - 1], o1 = mo.w[hi];   // this segment's slice of the parameters
+      sum_splits_kernel<<<2048, 256, 0, st>>>(a.grad + o0, a.splits, a.P, o1 - o0, grad + o0);
+      if ((e = hipGetLastError()) != hipSuccess) return hip_status(e, "weight-gradient sum launch");
+    }
+    hi = lo - 1;
+  }
+  const dim3 hb((unsigned)(d.width / 32 + 1), kHeadChunks);
   float* part = reinterpret_cast<float*>(ws + w.headp);
   if (d.precision == DDF_FP32)
-    head_grad_partial_kernel<float><<<hb, kThreads, 0, st>>>(reinterpret_cast<const float*>(ws + w.act + hslab),
-                                                             b.dzt, b.dzx, w.R, d.width, part);
+    head_grad_partial_kernel<float><<<hb, kThreads, 0, st>>>(reinterpret_cast<const float*>(p.h[nh]), dzt, dzx, w.R,
+                                                             d.width, part);
   else
-    head_grad_partial_kernel<__bf16><<<hb, kThreads, 0, st>>>(reinterpret_cast<const __bf16*>(ws + w.act + hslab),
-                                                              b.dzt, b.dzx, w.R, d.width, part);
-  head_grad_final_kernel<<<(unsigned)(d.width / 256 + 1), 256, 0, st>>>(part, d.width, d.n_out, grad + mo.w[d.n_hidden],
-                                                                       grad + mo.b[d.n_hidden]);
+    head_grad_partial_kernel<__bf16><<<hb, kThreads, 0, st>>>(reinterpret_cast<const __bf16*>(p.h[nh]), dzt, dzx,
+                                                              w.R, d.width, part);
+  head_grad_final_kernel<<<(unsigned)(d.width / 256 + 1), 256, 0, st>>>(part, d.width, d.n_out, grad + mo.w[nh],
+                                                                       grad + mo.b[nh]);
   return hip_status(hipGetLastError(), "head-gradient launch");
 }
 
 static int run_forward_train(const ddf_net_desc& d, const void* packed, const float* rays, int64_t n, float* zt,
                              float* zx, const TrainWs& w, uint8_t* ws, hipStream_t st) {
-  FwdArgs a{};
-  a.packed = static_cast<const uint8_t*>(packed);
-  a.lay = make_layout(d);
-  a.n_in = d.n_in; a.n_freq = d.n_freq; a.n_hidden = d.n_hidden; a.n_out = d.n_out;
-  a.in = rays; a.n = n; a.stride = n; a.mode = kModeTrain;
-  a.out0 = zt; a.out1 = zx;
-  a.act = ws + w.act; a.act_rows = w.R;
-  return hip_status(launch_forward(d, a, n, st), "training forward launch");
+  const TrainPtrs p = train_ptrs(d, w, ws);
+  return run_forward_rows(d, packed, rays, n, zt, zx, w, p, 0, d.n_hidden, st);
+}
+
+static int check_recompute(int recompute_every) {
+  if (recompute_every < 0) return fail(DDF_ERR_INVALID_ARG, "recompute_every = %d must be >= 0", recompute_every);
+  return DDF_OK;
 }
 
 }  // namespace ddf
@@ -702,22 +804,22 @@ using namespace ddf;
 
 extern "C" {
 
-size_t ddf_train_workspace_bytes(const ddf_net_desc* d, int64_t batch) {
-  if (check_train_desc(d) != DDF_OK || batch < 0) return 0;
-  return (size_t)train_ws(*d, batch, param_count_of(*d)).total;
+size_t ddf_train_workspace_bytes(const ddf_net_desc* d, int64_t batch, int32_t recompute_every) {
+  if (check_train_desc(d) != DDF_OK || batch < 0 || recompute_every < 0) return 0;
+  return (size_t)train_ws(*d, batch, param_count_of(*d), recompute_every).total;
 }
 
 int ddf_forward_train(const ddf_net_desc* d, const void* packed, const float* rays, int64_t n, float* z_t,
-                      float* z_xi, void* ws, size_t ws_bytes, void* stream) {
+                      float* z_xi, int32_t recompute_every, void* ws, size_t ws_bytes, void* stream) {
   int rc;
-  if ((rc = check_train_desc(d))) return rc;
+  if ((rc = check_train_desc(d)) || (rc = check_recompute(recompute_every))) return rc;
   if (n < 0 || n > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
   if (n == 0) return DDF_OK;
   if ((rc = check_ptr(packed, "packed")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(z_t, "z_t")) ||
       (rc = check_ptr(ws, "ws")))
     return rc;
   if (d->n_out > 1 && (rc = check_ptr(z_xi, "z_xi"))) return rc;
-  const TrainWs w = train_ws(*d, n, param_count_of(*d));
+  const TrainWs w = train_ws(*d, n, param_count_of(*d), recompute_every);
   if ((rc = check_rows(*d, w))) return rc;
   if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
   return run_forward_train(*d, packed, rays, n, z_t, d->n_out > 1 ? z_xi : z_t, w, static_cast<uint8_t*>(ws),
@@ -725,16 +827,17 @@ int ddf_forward_train(const ddf_net_desc* d, const void* packed, const float* ra
 }
 
 int ddf_backward(const ddf_net_desc* d, const void* packed, const float* rays, int64_t n, const float* grad_z_t,
-                 const float* grad_z_xi, float* grad_params, void* ws, size_t ws_bytes, void* stream) {
+                 const float* grad_z_xi, float* grad_params, int32_t recompute_every, void* ws, size_t ws_bytes,
+                 void* stream) {
   int rc;
-  if ((rc = check_train_desc(d))) return rc;
+  if ((rc = check_train_desc(d)) || (rc = check_recompute(recompute_every))) return rc;
   if (n < 0 || n > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
   if (n == 0) return DDF_OK;
-  if ((rc = check_ptr(packed, "packed")) || (rc = check_ptr(grad_z_t, "grad_z_t")) ||
+  if ((rc = check_ptr(packed, "packed")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(grad_z_t, "grad_z_t")) ||
       (rc = check_ptr(grad_params, "grad_params")) || (rc = check_ptr(ws, "ws")))
     return rc;
   if (d->n_out > 1 && (rc = check_ptr(grad_z_xi, "grad_z_xi"))) return rc;
-  const TrainWs w = train_ws(*d, n, param_count_of(*d));
+  const TrainWs w = train_ws(*d, n, param_count_of(*d), recompute_every);
   if ((rc = check_rows(*d, w))) return rc;
   if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
   hipStream_t st = (hipStream_t)stream;
@@ -744,7 +847,7 @@ int ddf_backward(const ddf_net_desc* d, const void* packed, const float* rays, i
                                                                   reinterpret_cast<float*>(wb + w.dzx), n, w.R);
   if ((rc = hip_status(hipGetLastError(), "gradient copy"))) return rc;
   g_err_clear();
-  return run_backward(*d, packed, w, wb, grad_params, st);
+  return run_backward(*d, packed, rays, n, w, wb, grad_params, st);
 }
 
 int ddf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* adam_v, void* packed,
@@ -754,7 +857,7 @@ int ddf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
   int rc;
   if ((rc = check_train_desc(d))) return rc;
   if (d->n_in != 6 || d->n_out != 2) return fail(DDF_ERR_INVALID_ARG, "ddf_train_step needs a DDF net (n_in 6, n_out 2)");
-  if ((rc = check_hp(hp))) return rc;
+  if ((rc = check_hp(hp)) || (rc = check_recompute(hp->recompute_every))) return rc;
   if (!(hp->l1_clamp > 0.f) || !(hp->bce_weight >= 0.f))
     return fail(DDF_ERR_INVALID_ARG, "loss hyper-parameters out of range");
   if (batch < 1 || batch > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "batch = %lld out of range", (long long)batch);
@@ -765,7 +868,7 @@ int ddf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
     return rc;
   if (grad_out && (rc = check_ptr(grad_out, "grad_out"))) return rc;
   const size_t P = param_count_of(*d);
-  const TrainWs w = train_ws(*d, batch, P);
+  const TrainWs w = train_ws(*d, batch, P, hp->recompute_every);
   if ((rc = check_rows(*d, w))) return rc;
   if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
   hipStream_t st = (hipStream_t)stream;
@@ -787,7 +890,7 @@ int ddf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
   loss_grad_kernel<<<(unsigned)((w.R + 255) / 256), 256, 0, st>>>(la);
   if ((rc = hip_status(hipGetLastError(), "loss launch"))) return rc;
   float* grad = grad_out ? grad_out : reinterpret_cast<float*>(wb + w.grad);
-  if ((rc = run_backward(*d, packed, w, wb, grad, st))) return rc;
+  if ((rc = run_backward(*d, packed, rays, batch, w, wb, grad, st))) return rc;
   return run_adam(*d, master, adam_m, adam_v, packed, grad, P, hp, nonfinite_flag, st);
 }
 
@@ -798,7 +901,7 @@ int sdf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
   int rc;
   if ((rc = check_train_desc(d))) return rc;
   if (d->n_in != 3 || d->n_out != 1) return fail(DDF_ERR_INVALID_ARG, "sdf_train_step needs an SDF net (n_in 3, n_out 1)");
-  if ((rc = check_hp(hp))) return rc;
+  if ((rc = check_hp(hp)) || (rc = check_recompute(hp->recompute_every))) return rc;
   if (n < 1 || n > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
   if ((rc = check_ptr(master, "master")) || (rc = check_ptr(adam_m, "adam_m")) || (rc = check_ptr(adam_v, "adam_v")) ||
       (rc = check_ptr(packed, "packed")) || (rc = check_ptr(points, "points")) || (rc = check_ptr(sdf_gt, "sdf_gt")) ||
@@ -807,7 +910,7 @@ int sdf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
     return rc;
   if (grad_out && (rc = check_ptr(grad_out, "grad_out"))) return rc;
   const size_t P = param_count_of(*d);
-  const TrainWs w = train_ws(*d, n, P);
+  const TrainWs w = train_ws(*d, n, P, hp->recompute_every);
   if ((rc = check_rows(*d, w))) return rc;
   if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
   hipStream_t st = (hipStream_t)stream;
@@ -826,7 +929,7 @@ int sdf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
   sdf_loss_grad_kernel<<<(unsigned)((w.R + 255) / 256), 256, 0, st>>>(la);
   if ((rc = hip_status(hipGetLastError(), "sdf loss launch"))) return rc;
   float* grad = grad_out ? grad_out : reinterpret_cast<float*>(wb + w.grad);
-  if ((rc = run_backward(*d, packed, w, wb, grad, st))) return rc;
+  if ((rc = run_backward(*d, packed, points, n, w, wb, grad, st))) return rc;
   return run_adam(*d, master, adam_m, adam_v, packed, grad, P, hp, nonfinite_flag, st);
 }
 

@@ -32,7 +32,7 @@ class NetDescC(ctypes.Structure):
 class TrainHParamsC(ctypes.Structure):
     _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
                 ("eps", ctypes.c_float), ("bce_weight", ctypes.c_float), ("l1_clamp", ctypes.c_float),
-                ("step", ctypes.c_int64)]
+                ("step", ctypes.c_int64), ("recompute_every", ctypes.c_int32)]
 
 
 _lib = None
@@ -50,9 +50,9 @@ SIGNATURES = {
     "ddf_query": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, _P]),
     "ddf_fp8_calib_workspace_bytes": (_SZ, [_D, _I64]),
     "ddf_fp8_act_scales": (ctypes.c_int, [_D, _P, _P, _I64, ctypes.POINTER(ctypes.c_float), _P, _SZ, _P]),
-    "ddf_train_workspace_bytes": (_SZ, [_D, _I64]),
-    "ddf_forward_train": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, _P, _SZ, _P]),
-    "ddf_backward": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "ddf_train_workspace_bytes": (_SZ, [_D, _I64, ctypes.c_int32]),
+    "ddf_forward_train": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, ctypes.c_int32, _P, _SZ, _P]),
+    "ddf_backward": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, _P, ctypes.c_int32, _P, _SZ, _P]),
     "ddf_train_step": (ctypes.c_int, [_D, _P, _P, _P, _P, _P, _P, _P, _I64, ctypes.POINTER(TrainHParamsC),
                                       _P, _P, _P, _P, _SZ, _P]),
     "sdf_trace_workspace_bytes": (_SZ, [_I64]),
@@ -223,27 +223,27 @@ def sdf_train_step(desc, precision, master, m, v, packed, points, sdf_gt, hp: Tr
     return loss_out, flag
 
 
-def train_workspace_bytes(desc, precision, batch) -> int:
+def train_workspace_bytes(desc, precision, batch, recompute_every=0) -> int:
     d = desc_c(desc, precision)
-    return int(lib().ddf_train_workspace_bytes(ctypes.byref(d), int(batch)))
+    return int(lib().ddf_train_workspace_bytes(ctypes.byref(d), int(batch), int(recompute_every)))
 
 
-def forward_train(desc, precision, packed, rays, ws):
+def forward_train(desc, precision, packed, rays, ws, recompute_every=0):
     d = desc_c(desc, precision)
     n = rays.shape[1]
     zt = torch.empty(n, dtype=torch.float32, device=rays.device)
     zx = torch.empty(n, dtype=torch.float32, device=rays.device)
     _check(lib().ddf_forward_train(ctypes.byref(d), _ptr(packed), _ptr(rays), n, _ptr(zt), _ptr(zx),
-                                   _ptr(ws), ws.numel(), _stream()))
+                                   int(recompute_every), _ptr(ws), ws.numel(), _stream()))
     return zt, zx
 
 
-def backward(desc, precision, packed, rays, grad_zt, grad_zx, ws):
+def backward(desc, precision, packed, rays, grad_zt, grad_zx, ws, recompute_every=0):
     d = desc_c(desc, precision)
     n = rays.shape[1]
     g = torch.empty(param_count(desc, precision), dtype=torch.float32, device=rays.device)
     _check(lib().ddf_backward(ctypes.byref(d), _ptr(packed), _ptr(rays), n, _ptr(grad_zt), _ptr(grad_zx),
-                              _ptr(g), _ptr(ws), ws.numel(), _stream()))
+                              _ptr(g), int(recompute_every), _ptr(ws), ws.numel(), _stream()))
     return g
 
 
@@ -270,3 +270,43 @@ def fp8_act_scales(desc, packed_fp32, rays) -> np.ndarray:
                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _ptr(ws), ws.numel(),
                                     _stream()))
     return out[:desc.n_hidden - 1]
+
+
+class DDFFunction(torch.autograd.Function):
+    """(z_t, z_xi) = f(params; rays): the library's training forward and backward as one
+    node of a torch.autograd graph, so that a distillation loss written with torch ops
+    back-propagates through the fused network.
+
+    params           float32 master vector [param_count(desc)] on the rays' device
+                     (packed into `precision` on every call).
+    rays             float32 [n_in][n] SoA inputs (rays [6][n]; SDF points [3][n]).
+    Returns the two logit vectors [n] (z_xi is zeros for a single-output network).  The
+    gradient flows to `params` only (none to the rays)."""
+
+    @staticmethod
+    def forward(ctx, params, rays, desc, precision="bf16", recompute_every=0):
+        _dev(params, torch.float32, "params")
+        _dev(rays, torch.float32, "rays")
+        packed = pack(desc, precision, params.detach())
+        ws = torch.empty(max(train_workspace_bytes(desc, precision, rays.shape[1], recompute_every), 256),
+                         dtype=torch.uint8, device=rays.device)
+        zt, zx = forward_train(desc, precision, packed, rays, ws, recompute_every)
+        if desc.n_out == 1:
+            zx = torch.zeros_like(zt)
+        ctx.save_for_backward(rays)
+        ctx.state = (desc, precision, packed, ws, recompute_every)
+        return zt, zx
+
+    @staticmethod
+    def backward(ctx, grad_zt, grad_zx):
+        (rays,) = ctx.saved_tensors
+        desc, precision, packed, ws, recompute_every = ctx.state
+        gzt = grad_zt.contiguous().to(torch.float32)
+        gzx = grad_zx.contiguous().to(torch.float32)
+        g = backward(desc, precision, packed, rays, gzt, gzx, ws, recompute_every)
+        return g, None, None, None, None
+
+
+def ddf_apply(params, rays, desc, precision="bf16", recompute_every=0):
+    """DDFFunction.apply with keyword defaults."""
+    return DDFFunction.apply(params, rays, desc, precision, recompute_every)
