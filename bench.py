@@ -6,9 +6,11 @@ point light at (0, 3, 0)) through the 12 x 1024 DDF (L = 10 encoding, 126
 features), random He-init weights (seed 0).  A timed step is one query of the
 whole batch (ray ingest, encoding, the fused layer chain and both heads) in
 the headline precision; the JSON line's `value` is the query throughput.
-Further legs run in the same invocation on the same inputs: the other query
-precisions, one distillation training step, and sphere tracing of a signed-
-distance MLP of the same size (the paper's baseline).  The float64 oracle is
+Further legs run in the same invocation: the other query precisions on the same
+rays; distillation training steps (65,536 rays through the 12 x 1024 net, and
+262,144 rays through the 16 x 1024 net with activations recomputed every 4
+layers, bf16 and fp32 each); and sphere tracing of a signed-distance MLP of the
+same size along the same rays (the paper's baseline).  The float64 oracle is
 timed on the host cores over a bounded sample of the same rays.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16]
@@ -128,8 +130,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--legs", default="precisions,train,trace,cpu",
-                    help="comma list of extra legs: precisions, train, trace, cpu, copy")
+    ap.add_argument("--legs", default="precisions,train,train_large,trace,cpu",
+                    help="comma list of extra legs: precisions, train, train_large, trace, cpu, copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
@@ -216,6 +218,10 @@ def main():
     if "train" in legs:
         out["train"] = train_leg(torch, ddf, I, dev, timer, args.steps)
 
+    if "train_large" in legs:
+        out["train_large"] = train_leg(torch, ddf, I, dev, timer, 4, batch=1 << 18, desc=I.NET_LARGE,
+                                       recompute_every=4, seed=1300, lr=3e-4)
+
     if "trace" in legs:
         out["sphere_trace"] = trace_leg(torch, ddf, I, dev, rays, timer, out, scene)
 
@@ -233,17 +239,20 @@ def train_flop_per_ray(desc):
     return fwd + dx + dw
 
 
-def train_leg(torch, ddf, I, dev, timer, steps, batch=65536):
-    """One distillation step per timed step: 65,536 rays (half surface-anchored, half free)
-    against 1,024 random ellipsoids, targets by exact ray casting on the GPU; bf16 forward
-    and backward with the fp32 master, then Adam and the repack."""
-    desc = I.NET_FULL
+def train_leg(torch, ddf, I, dev, timer, steps, batch=65536, desc=None, recompute_every=0, seed=1000, lr=1e-3):
+    """One distillation step per timed step: `batch` rays (half surface-anchored, half free)
+    against 1,024 random ellipsoids, targets by exact ray casting on the GPU; bf16 (then
+    fp32) forward and backward with the fp32 master, then Adam and the repack.  Defaults:
+    65,536 rays, 12 x 1024; the large configuration is 262,144 rays, 16 x 1024, activations
+    recomputed every 4 layers."""
+    desc = desc or I.NET_FULL
     scene = I.scene_ellipsoids(1024, 3)
     prims = torch.from_numpy(ddf.scene_prims(scene)).to(dev)
-    rays = torch.from_numpy(I.train_rays(scene, batch, 1000)).to(dev)
+    rays = torch.from_numpy(I.train_rays(scene, batch, seed)).to(dev)
     t_gt, hit = ddf.cast_targets(prims, rays)
     t_gt = torch.where(hit > 0, t_gt, torch.zeros_like(t_gt))
-    res = {"batch": batch, "net": "126-1024x12-2", "targets": "exact ray casting, 1024 ellipsoids",
+    res = {"batch": batch, "net": f"{desc.n_feat}-{desc.width}x{desc.n_hidden}-{desc.n_out}",
+           "recompute_every": recompute_every, "targets": "exact ray casting, 1024 ellipsoids",
            "hit_fraction": float(hit.float().mean().item())}
     fpr = train_flop_per_ray(desc)
     for prec in ("bf16", "fp32"):
@@ -251,14 +260,15 @@ def train_leg(torch, ddf, I, dev, timer, steps, batch=65536):
         m = torch.zeros_like(master)
         v = torch.zeros_like(master)
         packed = ddf.pack(desc, prec, master)
-        ws = torch.empty(ddf.train_workspace_bytes(desc, prec, batch), dtype=torch.uint8, device=dev)
+        ws = torch.empty(ddf.train_workspace_bytes(desc, prec, batch, recompute_every), dtype=torch.uint8,
+                         device=dev)
         loss = torch.empty(4, dtype=torch.float32, device=dev)
         flag = torch.empty(4, dtype=torch.int32, device=dev)
         step = [0]
 
         def one():
             step[0] += 1
-            hp = ddf.TrainHParamsC(1e-3, 0.9, 0.999, 1e-8, 0.3, 3.0, step[0])
+            hp = ddf.TrainHParamsC(lr, 0.9, 0.999, 1e-8, 0.3, 3.0, step[0], recompute_every)
             ddf.train_step(desc, prec, master, m, v, packed, rays, t_gt, hit, hp, ws, loss_out=loss, flag=flag)
         one()
         torch.cuda.synchronize()
@@ -268,7 +278,8 @@ def train_leg(torch, ddf, I, dev, timer, steps, batch=65536):
         res[prec] = {"ms_per_step": ms, "train_rays_per_s": batch / (ms * 1e-3),
                      "tflops": fpr * batch / (ms * 1e-3) / 1e12, "loss_first": l0,
                      "loss_last": float(loss[0].item()), "steps": step[0],
-                     "skipped": int(flag[0].item())}
+                     "skipped": int(flag[0].item()), "workspace_bytes": ws.numel()}
+        del ws
     res["flop_per_ray"] = fpr
     return res
 
