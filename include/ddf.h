@@ -199,6 +199,25 @@ int ddf_cast_targets(const float* prims, int32_t n_prims, const float* rays, int
 int ddf_scene_sdf(const float* prims, int32_t n_prims, const float* points, int64_t n, float* sdf,
                   void* stream);
 
+/* Self-consistency points for distillation (Sec. III-B; Sec. III-D replaces 30 % of each
+ * batch with them): along a ray that hits at t, the point moved forward by s must report
+ * t - s.  For every slot i of a batch of n rays with targets:
+ *   u[0][i] < frac: the slot takes the first hit ray j among the 1024 rays from index
+ *                   floor(u[1][i] n) on (cyclic), origin x_j + s d_j with s = u[2][i] t_j,
+ *                   direction d_j, t_out = t_j - s, hit_out = 1 (the slot is copied when
+ *                   none of them hits);
+ *   otherwise:      a copy of ray i, t_gt[i], hit[i].
+ *   rays, rays_out  device float32 [6][n] SoA (must not alias).
+ *   t_gt, t_out     device float32 [n].   hit, hit_out  device uint8 [n].
+ *   u               device float32 [3][n], uniforms in [0, 1) drawn by the caller.
+ *   frac            in [0, 1], e.g. 0.3. */
+int ddf_shift_rays(const float* rays, const float* t_gt, const uint8_t* hit, const float* u, float frac,
+                   int64_t n, float* rays_out, float* t_out, uint8_t* hit_out, void* stream);
+
+/* The distillation learning rate at `step` (host function, Sec. III-D): cosine decay from
+ * lr0 to final_frac * lr0 over `total` steps, held after; e.g. (3e-3, 0.05, 30000). */
+float ddf_lr_cosine(int64_t step, int64_t total, float lr0, float final_frac);
+
 /* One fitting step of an SDF MLP (desc n_in 3, n_out 1) by Adam on the L1 error
  *   loss = mean over points of |s(p) - sdf_gt(p)|
  * with the same forward, backward, Adam and repack as ddf_train_step (hp->bce_weight and

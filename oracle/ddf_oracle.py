@@ -354,3 +354,43 @@ def lr_schedule(step, total=30000, lr0=3e-3, final_frac=0.05):
     s = min(max(step, 0), total)
     lo = lr0 * final_frac
     return lo + 0.5 * (lr0 - lo) * (1.0 + math.cos(math.pi * s / total))
+
+
+SHIFT_WALK = 1024   # rays searched for a hit from the drawn start index
+
+
+def shift_rays(rays, t_gt, hit, u, frac):
+    """Self-consistency points (Sec. III-B: along a ray that hits at t, the point moved
+    forward by s must report t - s; Sec. III-D: 30 % of each batch).
+
+    Slot i with u[0][i] < frac takes the first hit ray j among the SHIFT_WALK rays from
+    index floor(u[1][i] n) on (cyclically) and becomes the ray from x_j + s d_j along d_j
+    with target t_j - s, s = u[2][i] t_j; every other slot, and a selected slot that finds
+    no hit, keeps its own ray.  The index decisions (u < frac, floor(u n)) and s are taken
+    in float32, as the uniforms are float32 draws; origins and targets come back in float64.
+    Returns (rays [6][n] float64, t [n] float64, hit [n] uint8, src [n] int64, shifted [n] bool)."""
+    r = np.asarray(rays, dtype=np.float64)
+    n = r.shape[1]
+    t = np.asarray(t_gt, dtype=np.float64).copy()
+    h = np.asarray(hit).astype(np.uint8).copy()
+    u32 = np.asarray(u, dtype=np.float32)
+    out = r.copy()
+    src = np.arange(n)
+    shifted = np.zeros(n, dtype=bool)
+    hit_idx = np.asarray(hit).astype(bool)
+    for i in range(n):
+        if not (u32[0, i] < np.float32(frac)):
+            continue
+        c = min(int(np.floor(u32[1, i] * np.float32(n))), n - 1)
+        for k in range(min(n, SHIFT_WALK)):
+            j = (c + k) % n
+            if hit_idx[j]:
+                s = float(np.float32(u32[2, i] * np.float32(t_gt[j])))
+                out[0:3, i] = r[0:3, j] + s * r[3:6, j]
+                out[3:6, i] = r[3:6, j]
+                t[i] = float(t_gt[j]) - s
+                h[i] = 1
+                src[i] = j
+                shifted[i] = True
+                break
+    return out, t, h, src, shifted

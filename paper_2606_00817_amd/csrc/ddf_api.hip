@@ -350,6 +350,62 @@ int ddf_cast_targets(const float* prims, int32_t n_prims, const float* rays, int
   return hip_status(hipGetLastError(), "ddf_cast_targets launch");
 }
 
+// Self-consistency points (Sec. III-B, III-D): slot i with u[0][i] < frac takes the first hit
+// ray j among the kShiftWalk rays from floor(u[1][i] n) on (cyclically) and moves its origin
+// forward by s = u[2][i] t_j, target t_j - s; other slots (and a selected slot that finds no
+// hit) are copied.
+constexpr int64_t kShiftWalk = 1024;
+
+__global__ void shift_kernel(const float* rays, const float* t_gt, const uint8_t* hit, const float* u, float frac,
+                             int64_t n, float* rays_out, float* t_out, uint8_t* hit_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t j = i;
+  float s = 0.f;
+  bool shifted = false;
+  if (u[i] < frac) {
+    int64_t c = (int64_t)(u[n + i] * (float)n);
+    if (c >= n) c = n - 1;
+    const int64_t walk = n < kShiftWalk ? n : kShiftWalk;
+    for (int64_t k = 0; k < walk; ++k, c = c + 1 == n ? 0 : c + 1)
+      if (hit[c]) { j = c; shifted = true; break; }
+    if (shifted) s = u[2 * n + i] * t_gt[j];
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float x = rays[a * n + j], d = rays[(3 + a) * n + j];
+    rays_out[a * n + i] = shifted ? fmaf(s, d, x) : x;
+    rays_out[(3 + a) * n + i] = d;
+  }
+  t_out[i] = shifted ? t_gt[j] - s : t_gt[i];
+  hit_out[i] = shifted ? 1 : hit[i];
+}
+
+int ddf_shift_rays(const float* rays, const float* t_gt, const uint8_t* hit, const float* u, float frac, int64_t n,
+                   float* rays_out, float* t_out, uint8_t* hit_out, void* stream) {
+  int rc;
+  if (n < 0 || n > (int64_t)INT32_MAX) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (!(frac >= 0.f && frac <= 1.f)) return fail(DDF_ERR_INVALID_ARG, "frac must be in [0, 1]");
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(rays, "rays")) || (rc = check_ptr(t_gt, "t_gt")) || (rc = check_ptr(hit, "hit")) ||
+      (rc = check_ptr(u, "u")) || (rc = check_ptr(rays_out, "rays_out")) || (rc = check_ptr(t_out, "t_out")) ||
+      (rc = check_ptr(hit_out, "hit_out")))
+    return rc;
+  if (rays_out == rays || t_out == t_gt || hit_out == hit)
+    return fail(DDF_ERR_INVALID_ARG, "outputs must not alias the inputs");
+  g_err[0] = 0;
+  shift_kernel<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(rays, t_gt, hit, u, frac, n, rays_out,
+                                                                            t_out, hit_out);
+  return hip_status(hipGetLastError(), "ddf_shift_rays launch");
+}
+
+float ddf_lr_cosine(int64_t step, int64_t total, float lr0, float final_frac) {
+  const double s = (double)(step < 0 ? 0 : (step > total ? total : step));
+  const double lo = (double)lr0 * final_frac;
+  const double c = total > 0 ? cos(M_PI * s / (double)total) : 1.0;
+  return (float)(lo + 0.5 * ((double)lr0 - lo) * (1.0 + c));
+}
+
 int ddf_scene_sdf(const float* prims, int32_t n_prims, const float* points, int64_t n, float* sdf, void* stream) {
   int rc;
   if (n_prims < 1) return fail(DDF_ERR_INVALID_ARG, "n_prims must be >= 1");

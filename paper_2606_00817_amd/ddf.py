@@ -61,6 +61,8 @@ SIGNATURES = {
     "sdf_eval": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P]),
     "ddf_cast_targets": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P, _P, _P]),
     "ddf_scene_sdf": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P, _P]),
+    "ddf_shift_rays": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float, _I64, _P, _P, _P, _P]),
+    "ddf_lr_cosine": (ctypes.c_float, [_I64, _I64, ctypes.c_float, ctypes.c_float]),
     "sdf_train_step": (ctypes.c_int, [_D, _P, _P, _P, _P, _P, _P, _I64, ctypes.POINTER(TrainHParamsC),
                                       _P, _P, _P, _P, _SZ, _P]),
 }
@@ -199,6 +201,25 @@ def cast_targets(prims: torch.Tensor, rays: torch.Tensor):
     hit = torch.empty(n, dtype=torch.uint8, device=rays.device)
     _check(lib().ddf_cast_targets(_ptr(prims), prims.shape[0], _ptr(rays), n, _ptr(t), _ptr(hit), _stream()))
     return t, hit
+
+
+def shift_rays(rays: torch.Tensor, t_gt: torch.Tensor, hit: torch.Tensor, u: torch.Tensor, frac=0.3):
+    """Self-consistency points replacing a fraction of a batch (see ddf_shift_rays)."""
+    _dev(rays, torch.float32, "rays")
+    _dev(t_gt, torch.float32, "t_gt")
+    _dev(hit, torch.uint8, "hit")
+    _dev(u, torch.float32, "u")
+    n = rays.shape[1]
+    ro = torch.empty_like(rays)
+    to = torch.empty_like(t_gt)
+    ho = torch.empty_like(hit)
+    _check(lib().ddf_shift_rays(_ptr(rays), _ptr(t_gt), _ptr(hit), _ptr(u), float(frac), n, _ptr(ro), _ptr(to),
+                                _ptr(ho), _stream()))
+    return ro, to, ho
+
+
+def lr_cosine(step, total=30000, lr0=3e-3, final_frac=0.05) -> float:
+    return float(lib().ddf_lr_cosine(int(step), int(total), float(lr0), float(final_frac)))
 
 
 def scene_sdf(prims: torch.Tensor, points: torch.Tensor):

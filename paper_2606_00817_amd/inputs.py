@@ -301,6 +301,13 @@ def mixed_rays(scene: Scene, n: int, seed: int) -> np.ndarray:
     return np.ascontiguousarray(allr[:, perm])
 
 
+def uniforms(rows: int, n: int, seed: int) -> np.ndarray:
+    """float32 [rows][n] uniform draws in [0, 1) (e.g. the selection, start index and shift
+    of the self-consistency points of a training batch)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.ascontiguousarray(rng.random((rows, n)).astype(np.float32))
+
+
 def sdf_train_points(scene: Scene, n: int, seed: int, sigma: float = 0.05) -> np.ndarray:
     """SDF fitting samples, float32 [3, N]: half uniform in the box, half surface points
     displaced by isotropic N(0, sigma^2) noise."""

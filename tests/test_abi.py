@@ -79,3 +79,12 @@ def test_validation_errors_before_any_launch():
 @pytest.mark.parametrize("code", [0, -1, -2, -3, -4])
 def test_status_strings(code):
     assert ddf.lib().ddf_status_string(code)
+
+
+def test_lr_cosine_matches_oracle():
+    """The host-side learning-rate schedule against the oracle's cosine decay."""
+    from oracle import ddf_oracle as O
+    for step in (0, 1, 7, 15000, 29999, 30000, 45000):
+        assert abs(ddf.lr_cosine(step) - O.lr_schedule(step)) <= 1e-6 * 3e-3
+    assert abs(ddf.lr_cosine(30000) - 0.05 * 3e-3) <= 1e-9
+    assert abs(ddf.lr_cosine(0, 100, 1.0, 0.5) - 1.0) <= 1e-7

@@ -256,3 +256,68 @@ def test_sdf_train_step_matches_oracle():
     assert float(loss.cpu()[0]) == pytest.approx(ref_loss, rel=1e-5)
     worst = max(e for e, _ in _per_layer_errors(desc, grad.cpu().numpy().astype(np.float64), ref_grad))
     assert worst < 2e-4
+
+
+def test_shift_rays_matches_oracle():
+    """The self-consistency batch on the GPU against the oracle: the same slots move and take
+    the same source ray (directions are copied bit for bit), origins and targets to float32
+    rounding, hit flags exact; over a ragged batch of 100,003 rays."""
+    dev = cuda()
+    n = 100003
+    sc = I.scene_ellipsoids(1024, 3)
+    rays = I.train_rays(sc, n, 1210)
+    tg, hit, _ = G.intersect_soa(sc, rays)
+    t32 = np.where(hit, tg, 0).astype(np.float32)
+    u = I.uniforms(3, n, 1211)
+    ro, to, ho = ddf.shift_rays(_t(rays, dev), _t(t32, dev), _t(hit.astype(np.uint8), dev), _t(u, dev), 0.3)
+    torch.cuda.synchronize()
+    ro, to, ho = ro.cpu().numpy(), to.cpu().numpy(), ho.cpu().numpy()
+    r64, t64, h64, src, sh = O.shift_rays(rays, t32, hit, u, 0.3)
+    np.testing.assert_array_equal(ho, h64)
+    np.testing.assert_array_equal(ro[3:6], r64[3:6].astype(np.float32))
+    np.testing.assert_array_equal(ro[:, ~sh], rays[:, ~sh])
+    np.testing.assert_array_equal(to[~sh], t32[~sh])
+    tol = 4 * 2.0 ** -24 * (np.abs(r64[0:3]).max() + np.abs(t32).max() + 1)
+    assert np.abs(ro[0:3] - r64[0:3]).max() <= tol
+    assert np.abs(to - t64).max() <= tol
+    print(f"shift: {sh.mean():.3f} of the slots moved")
+
+
+def test_distillation_recipe_trains():
+    """The paper's recipe on a 4 x 256 bf16 net: batches of 16,384 rays with 30 % replaced by
+    self-consistency points, cosine learning rate from 3e-3: 60 steps lower the loss on a fixed
+    held-out batch (evaluated with the same loss through the fp32 path)."""
+    dev = cuda()
+    desc = I.NetDesc(6, 10, 4, 256, 2)
+    B = 16384
+    sc = I.scene_ellipsoids(1024, 3)
+    prims = _t(ddf.scene_prims(sc), dev)
+    master = _t(I.he_init(desc, 5), dev)
+    m = torch.zeros_like(master); v = torch.zeros_like(master)
+    packed = ddf.pack(desc, "bf16", master)
+    ws = torch.empty(ddf.train_workspace_bytes(desc, "bf16", B), dtype=torch.uint8, device=dev)
+    held = _t(I.train_rays(sc, 8192, 1220), dev)
+    ht, hh = ddf.cast_targets(prims, held)
+    ht = torch.where(hh > 0, ht, torch.zeros_like(ht))
+
+    def held_loss():
+        zt, zx = ddf.forward_train(desc, "fp32", ddf.pack(desc, "fp32", master), held,
+                                   torch.empty(ddf.train_workspace_bytes(desc, "fp32", 8192), dtype=torch.uint8,
+                                               device=dev))
+        (tot, _, _), _, _ = O.loss_terms(zt.cpu().numpy().astype(np.float64), zx.cpu().numpy().astype(np.float64),
+                                         ht.cpu().numpy().astype(np.float64), hh.cpu().numpy())
+        return tot
+
+    l0 = held_loss()
+    pool = [_t(I.train_rays(sc, B, 1230 + j), dev) for j in range(6)]
+    for s in range(1, 61):
+        rays = pool[s % len(pool)]
+        t, h = ddf.cast_targets(prims, rays)
+        t = torch.where(h > 0, t, torch.zeros_like(t))
+        rs, ts, hs = ddf.shift_rays(rays, t, h, _t(I.uniforms(3, B, 5230 + s), dev), 0.3)
+        hp = ddf.TrainHParamsC(ddf.lr_cosine(s - 1), 0.9, 0.999, 1e-8, O.BCE_WEIGHT, O.L1_CLAMP, s)
+        loss, flag = ddf.train_step(desc, "bf16", master, m, v, packed, rs, ts, hs, hp, ws)
+    torch.cuda.synchronize()
+    l1 = held_loss()
+    print(f"recipe: held-out loss {l0:.4f} -> {l1:.4f}")
+    assert int(flag.cpu()[0]) == 0 and l1 < 0.7 * l0

@@ -454,3 +454,28 @@ def test_sdf_loss_gradient_matches_central_differences():
         pm = params.copy(); pm[k] -= h
         fd = (O.sdf_loss_and_grad(desc, pp, pts, gt)[0] - O.sdf_loss_and_grad(desc, pm, pts, gt)[0]) / (2 * h)
         assert abs(fd - grad[k]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9
+
+
+def test_shift_rays_targets_match_exact_casting():
+    """Self-consistency points: the exact cast from a moved origin along its direction hits at
+    the shifted target (to the float32 rounding of t); unselected slots are untouched; about
+    frac of the slots move; frac = 0 and an all-miss batch change nothing."""
+    sc = I.scene_ellipsoids(64, 3)
+    n = 2000
+    rays = I.train_rays(sc, n, 77)
+    tg, hit, _ = G.intersect_soa(sc, rays)
+    t32 = np.where(hit, tg, 0).astype(np.float32)
+    u = np.random.default_rng(1).random((3, n)).astype(np.float32)
+    ro, to, ho, src, sh = O.shift_rays(rays, t32, hit, u, 0.3)
+    assert abs(sh.mean() - 0.3) < 0.04 and ho[sh].all()
+    t2, h2, _ = G.intersect(sc, ro[0:3, sh].T, ro[3:6, sh].T)
+    assert h2.all()
+    assert np.abs(t2 - to[sh]).max() <= 4e-7 * max(1.0, t32.max())
+    assert np.all(to[sh] > 0) and np.all(to[sh] <= t32[src[sh]])
+    np.testing.assert_array_equal(ro[:, ~sh], rays[:, ~sh].astype(np.float64))
+    np.testing.assert_array_equal(ro[3:6, sh], rays[3:6, src[sh]].astype(np.float64))
+    assert hit[src[sh]].all()
+    ro0, to0, _, _, sh0 = O.shift_rays(rays, t32, hit, u, 0.0)
+    assert not sh0.any() and np.array_equal(ro0, rays.astype(np.float64))
+    _, _, _, _, shm = O.shift_rays(rays, t32, np.zeros(n, np.uint8), u, 1.0)
+    assert not shm.any()
