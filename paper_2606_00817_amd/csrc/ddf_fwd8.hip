@@ -37,6 +37,15 @@ __device__ inline i32x8 buf_b8(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
   return i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 }
 
+// The lane index, recomputed where it is used: the empty asm makes the value opaque, so the
+// per-lane addresses derived from it are formed in the epilogue instead of being hoisted to
+// the kernel start, kept live across every layer and spilled.
+__device__ inline int fresh_lane() {
+  int l = (int)(threadIdx.x & 63);
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
 // Four values in [0, 448], already divided by the next layer's scale, as four e4m3 codes in
 // one word (element i in byte i), rounded to nearest even.
 __device__ inline uint32_t pack_e4m3(float y0, float y1, float y2, float y3) {
@@ -229,9 +238,10 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
     float bv[kBL];
     {
       const float* bl = bias_all + (int64_t)l * WIDTH + wave * kNW;
+      const int el = fresh_lane();
 #pragma unroll
       for (int j = 0; j < kBL; ++j)
-        if (j * 64 + lane < kNW) bv[j] = bl[j * 64 + lane];
+        if (j * 64 + el < kNW) bv[j] = bl[j * 64 + el];
     }
     const float* bias = bsm;
     // Operand roles are swapped (weights as the first matrix-core operand): register group q
@@ -263,11 +273,13 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
       if (WAVES == 8 && p == 1)
         preload8<NTP, WIDTH / 64>(ring, a.packed + a.lay.w_off[last ? l : l + 1], wave * NTW, lane, WIDTH);
       if (p == 0) {
+        const int el = fresh_lane();
 #pragma unroll
         for (int j = 0; j < kBL; ++j)
-          if (j * 64 + lane < kNW) bsm[wave * kNW + j * 64 + lane] = bv[j];
+          if (j * 64 + el < kNW) bsm[wave * kNW + j * 64 + el] = bv[j];
       }
       if (p == 1) __syncthreads();   // every wave is done reading this layer's input
+      const int el = fresh_lane();
       // the two epilogues are separate uniform branches, so that neither carries the
       // other's tests inside its unrolled loops
       if (last) {
@@ -276,7 +288,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
         const float* hw1 = a.n_out > 1 ? hw + WIDTH : hw;
 #pragma unroll
         for (int t = 0; t < NTP; ++t) {
-          const int nb = (tile0 + t) * 32 + 4 * (lane >> 5);
+          const int nb = (tile0 + t) * 32 + 4 * (el >> 5);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const f32x4 b4 = *reinterpret_cast<const f32x4*>(bias + nb + 8 * q);
@@ -299,15 +311,15 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
           for (int rt = 0; rt < kRT8; ++rt)
 #pragma unroll
             for (int t = 0; t < NTP; ++t) {
-              const int nb = (wave * NTW + t) * 32 + 4 * (lane >> 5);
+              const int nb = (wave * NTW + t) * 32 + 4 * (el >> 5);
 #pragma unroll
               for (int q = 0; q < 4; ++q)
-                *reinterpret_cast<uint32_t*>(X + (rt * 32 + (lane & 31)) * LDX + nb + 8 * q) = hold[rt][t][q];
+                *reinterpret_cast<uint32_t*>(X + (rt * 32 + (el & 31)) * LDX + nb + 8 * q) = hold[rt][t][q];
             }
         }
 #pragma unroll
         for (int t = 0; t < NTP; ++t) {
-          const int nb = (tile0 + t) * 32 + 4 * (lane >> 5);
+          const int nb = (tile0 + t) * 32 + 4 * (el >> 5);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             // relu(acc dq + b) / s_A,next in one rounding: the scales are powers of two, so
@@ -326,7 +338,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
               if (p == 0)
                 hold[rt][t][q] = w;
               else
-                *reinterpret_cast<uint32_t*>(X + (rt * 32 + (lane & 31)) * LDX + nb + 8 * q) = w;
+                *reinterpret_cast<uint32_t*>(X + (rt * 32 + (el & 31)) * LDX + nb + 8 * q) = w;
             }
           }
           __builtin_amdgcn_sched_barrier(0);
@@ -334,13 +346,14 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
       }
     }
     if (last) {
+      const int el = fresh_lane();
 #pragma unroll
       for (int rt = 0; rt < kRT8; ++rt) {
         const float s0 = hp0[rt] + __shfl_xor(hp0[rt], 32);
         const float s1 = hp1[rt] + __shfl_xor(hp1[rt], 32);
-        if (lane < 32) {
-          headp[wave][rt * 32 + lane][0] = s0;
-          headp[wave][rt * 32 + lane][1] = s1;
+        if (el < 32) {
+          headp[wave][rt * 32 + el][0] = s0;
+          headp[wave][rt * 32 + el][1] = s1;
         }
       }
     }
