@@ -67,6 +67,43 @@ class NetDesc:
         return res
 
 
+@dataclasses.dataclass(frozen=True)
+class HashDesc:
+    """Shape of the hash-grid field (Sec. III-D): a multiresolution hash encoding of the
+    origin, a sinusoidal code of the direction, and a small ReLU MLP."""
+    n_levels: int = 16
+    n_feat: int = 2          # features per level
+    log2_table: int = 19     # entries per level (at most)
+    base_res: int = 16       # resolution of the coarsest level
+    growth: float = 1.5      # resolution factor between levels
+    dir_bands: int = 4
+    width: int = 64
+    n_hidden: int = 2
+    n_out: int = 2
+    box_half: float = BOX_HALF
+
+
+HASH_PAPER = HashDesc()                                   # the paper's 52 MB field
+HASH_SMALL = HashDesc(n_levels=6, log2_table=12, base_res=4, growth=2.0, width=64)   # tests: dense and hashed levels
+
+
+def hash_params(desc: HashDesc, n_entries: int, seed: int, table_std: float = 1e-4) -> np.ndarray:
+    """Flat float32 parameters of a hash-grid field: the table ([n_entries][n_feat],
+    N(0, table_std), level after level) then the MLP (He-normal weights, N(0, 0.1) biases,
+    heads N(0, 1/fan_in)).  n_entries comes from the caller (the library's or the oracle's
+    level layout); the MLP input width is n_levels n_feat + 3 (1 + 2 dir_bands)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = [rng.standard_normal(n_entries * desc.n_feat) * table_std]
+    fan_in = desc.n_levels * desc.n_feat + 3 * (1 + 2 * desc.dir_bands)
+    for layer in range(desc.n_hidden + 1):
+        out = desc.width if layer < desc.n_hidden else desc.n_out
+        std = math.sqrt(2.0 / fan_in) if layer < desc.n_hidden else math.sqrt(1.0 / fan_in)
+        parts.append(rng.standard_normal(out * fan_in) * std)
+        parts.append(rng.standard_normal(out) * 0.1)
+        fan_in = out
+    return np.concatenate(parts).astype(np.float32)
+
+
 # Workload nets.
 NET_TINY = NetDesc(6, 4, 4, 128, 2)        # 54 -> 128 x4 -> 2
 NET_FULL = NetDesc(6, 10, 12, 1024, 2)     # 126 -> 1024 x12 -> 2 (46.7 MB fp32)
