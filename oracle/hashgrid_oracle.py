@@ -30,6 +30,12 @@ Readings where the paper is silent (each also listed in the design notes):
 * Level l: s = p N_l with p in [0, 1]^3; the cell's lower vertex is
   c = min(floor(s), N_l - 1) per axis (so p = 1 lies in the last cell), the
   weights w = s - c.
+* The cell is an integer decision taken from floating point, so for parity with
+  a float32 kernel the oracle can form p and s the way that kernel does
+  (coords="fp32": p = fl(fl(x + h) fl(0.5 / h)) clamped, s = fl(p N), each
+  operation rounded to float32); the interpolation from s on stays exact.  At
+  the finest levels (N ~ 7000) float32 grid coordinates are off by up to ~1e-3
+  cell, so this matters.  coords="exact" (the default) uses float64 throughout.
 * The table is laid out level after level, F floats per entry; level l holds
   min(T, (N_l + 1)^3) entries.  The MLP parameters follow the table: W1 [64 x D],
   b1, W2 [64 x 64], b2, heads [2 x 64], [2], with D = 2 L + 3 (1 + 2 bands).
@@ -108,8 +114,13 @@ def split(desc, params):
 # Encoding
 # ----------------------------------------------------------------------------
 
-def unit_coords(desc, x):
+def unit_coords(desc, x, coords="exact"):
     """Points [N, 3] in the object box -> [0, 1]^3 (clamped)."""
+    if coords == "fp32":
+        h = np.float32(desc.box_half)
+        inv = np.float32(0.5) / h
+        p = (np.asarray(x, dtype=np.float32) + h) * inv
+        return np.clip(p, np.float32(0), np.float32(1))
     lo = -desc.box_half
     return np.clip((np.asarray(x, dtype=np.float64) - lo) / (2 * desc.box_half), 0.0, 1.0)
 
@@ -125,13 +136,13 @@ def vertex_index(N, dense, T, v):
     return h % T
 
 
-def corners(desc, x):
+def corners(desc, x, coords="exact"):
     """Per level: (indices [N, 8] into the whole table, weights [N, 8]) of the trilinear lookup."""
-    p = unit_coords(desc, x)
+    p = unit_coords(desc, x, coords)
     T = 1 << desc.log2_table
     out = []
     for N, e, dense, off in levels(desc):
-        s = p * N
+        s = (p * np.float32(N)).astype(np.float64) if coords == "fp32" else p * N
         c = np.minimum(np.floor(s), N - 1)
         w = s - c
         idx = np.empty((len(p), 8), dtype=np.int64)
@@ -144,17 +155,17 @@ def corners(desc, x):
     return out
 
 
-def encode_position(desc, table, x):
+def encode_position(desc, table, x, coords="exact"):
     """[N, L F] interpolated features, level-major."""
-    feats = [np.einsum('nk,nkf->nf', wt, table[idx]) for idx, wt in corners(desc, x)]
+    feats = [np.einsum('nk,nkf->nf', wt, table[idx]) for idx, wt in corners(desc, x, coords)]
     return np.concatenate(feats, axis=1)
 
 
-def encode(desc, params, rays):
+def encode(desc, params, rays, coords="exact"):
     """The MLP input [N, D] of rays [6, N]: position code then direction code."""
     r = np.asarray(rays, dtype=np.float64)
     table, _ = split(desc, params)
-    pos = encode_position(desc, table, r[0:3].T)
+    pos = encode_position(desc, table, np.asarray(rays)[0:3].T, coords)
     return np.concatenate([pos, O.encode(r[3:6].T, desc.dir_bands)], axis=1)
 
 
@@ -172,18 +183,18 @@ def mlp_forward(mlp, g):
     return hs, h @ Wh.T + bh
 
 
-def hash_query(desc, params, rays):
+def hash_query(desc, params, rays, coords="exact"):
     """(t, xi, z_t, z_xi) per ray [6, N]."""
     _, mlp = split(desc, params)
-    _, z = mlp_forward(mlp, encode(desc, params, rays))
+    _, z = mlp_forward(mlp, encode(desc, params, rays, coords))
     return O.softplus(z[:, 0]), O.sigmoid(z[:, 1]), z[:, 0], z[:, 1]
 
 
-def backward(desc, params, rays, dz):
+def backward(desc, params, rays, dz, coords="exact"):
     """Gradient of sum(dz * z) with respect to every parameter (flat, float64)."""
     table, mlp = split(desc, params)
     r = np.asarray(rays, dtype=np.float64)
-    g = encode(desc, params, rays)
+    g = encode(desc, params, rays, coords)
     hs, _ = mlp_forward(mlp, g)
     grads = []
     delta = np.asarray(dz, dtype=np.float64)
@@ -197,15 +208,15 @@ def backward(desc, params, rays, dz):
     # delta is now dL/dg; the position part scatters to the table with the lookup weights
     gtab = np.zeros_like(table)
     F = desc.n_feat
-    for l, (idx, wt) in enumerate(corners(desc, r[0:3].T)):
+    for l, (idx, wt) in enumerate(corners(desc, np.asarray(rays)[0:3].T, coords)):
         dfeat = delta[:, l * F:(l + 1) * F]
         for k in range(8):
             np.add.at(gtab, idx[:, k], wt[:, k, None] * dfeat)
     return np.concatenate([gtab.ravel()] + [np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
 
 
-def loss_and_grad(desc, params, rays, t_gt, hit):
+def loss_and_grad(desc, params, rays, t_gt, hit, coords="exact"):
     """Distillation loss (the same terms as the sinusoidal field) and its gradient."""
-    _, _, zt, zx = hash_query(desc, params, rays)
+    _, _, zt, zx = hash_query(desc, params, rays, coords)
     terms, dzt, dzx = O.loss_terms(zt, zx, t_gt, hit)
-    return terms, backward(desc, params, rays, np.stack([dzt, dzx], axis=1))
+    return terms, backward(desc, params, rays, np.stack([dzt, dzx], axis=1), coords)
