@@ -228,6 +228,53 @@ int sdf_train_step(const ddf_net_desc* desc, float* master, float* adam_m, float
                    float* loss_out, int32_t* nonfinite_flag, float* grad_out, void* ws, size_t ws_bytes,
                    void* stream);
 
+/* ------------------------------------------------------------------ hash-grid field */
+
+/* The paper's fast field (Sec. III-D): the ray origin through a multiresolution hash
+ * encoding (level l of resolution N_l = floor(base_res growth^l) over the box
+ * [-box_half, box_half]^3, n_feat features per vertex, trilinear lookups, dense indexing
+ * while (N_l + 1)^3 <= 2^log2_table, else the spatial hash (v0 XOR 2654435761 v1 XOR
+ * 805459861 v2) mod 2^log2_table), the direction through dir_bands sinusoidal bands
+ * ([d, sin(pi 2^k d), cos(pi 2^k d)]), a ReLU MLP of n_hidden layers of width 64, and the
+ * heads t = softplus(z_t), xi = sigmoid(z_xi).  The paper's field: 16 levels, 2 features,
+ * 2^19, 16, 1.5, 4 bands, 2 x 64, box 1.5: 13.07M parameters, 52 MB in float32.
+ * Points outside the box are clamped to it; in float32, p = (x + box_half) (0.5 / box_half)
+ * clamped to [0, 1], s = p N, and the cell is min(floor(s), N - 1).  Compiled shapes:
+ * n_levels 16 or 6, dir_bands 4, n_feat 2, width 64, n_hidden 2, n_out 2; any other desc
+ * returns DDF_ERR_UNSUPPORTED (DDF_ERR_INVALID_ARG for base_res < 1, growth outside
+ * [1, 8], box_half <= 0), and the finest resolution must stay below 1e6. */
+typedef struct {
+  int32_t n_levels, n_feat, log2_table, base_res;
+  float growth;
+  int32_t dir_bands, width, n_hidden, n_out;
+  float box_half;
+} ddf_hash_desc;
+
+/* Parameter vector length (0 for an unsupported desc): the table, level after level,
+ * n_feat floats per entry; then W1 [64][D], b1, W_l [64][64], b_l, heads [2][64], [2]
+ * with D = 2 n_levels + 3 (1 + 2 dir_bands). */
+size_t ddf_hash_param_count(const ddf_hash_desc* desc);
+
+/* Level `level`'s resolution, table entries, entry offset and whether it is hashed
+ * (host; any output pointer may be NULL). */
+int ddf_hash_level(const ddf_hash_desc* desc, int32_t level, int32_t* resolution, int64_t* entries,
+                   int64_t* offset, int32_t* hashed);
+
+/* Query: params device float32 [ddf_hash_param_count]; rays [6][n]; t, xi [n]. */
+int ddf_hash_query(const ddf_hash_desc* desc, const float* params, const float* rays, int64_t n,
+                   float* t, float* xi, void* stream);
+
+/* One distillation step of the hash-grid field: forward, the loss of ddf_train_step,
+ * backward (the table gradient gathered with float atomics: its summation order is not
+ * fixed; every other reduction is), Adam over all parameters (skipped on a non-finite
+ * gradient).  Arguments as ddf_train_step; hp->recompute_every is ignored; workspace
+ * ddf_hash_train_workspace_bytes(desc, batch). */
+size_t ddf_hash_train_workspace_bytes(const ddf_hash_desc* desc, int64_t batch);
+int ddf_hash_train_step(const ddf_hash_desc* desc, float* params, float* adam_m, float* adam_v,
+                        const float* rays, const float* t_gt, const uint8_t* hit_gt, int64_t batch,
+                        const ddf_train_hparams* hp, float* loss_out, int32_t* nonfinite_flag,
+                        float* grad_out, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,736 @@
+// The hash-grid DDF (Sec. III-D): the ray origin through a multiresolution hash encoding
+// (L levels, 2 features each, trilinear lookups in per-level tables), the direction through
+// sinusoidal bands, then a ReLU MLP of width 64 and the two heads.
+//
+// Parameters are one fp32 vector: the table (level after level, 2 floats per entry), then
+// W1 [64][D], b1, hidden W_l [64][64], b_l, heads [n_out][64], [n_out] (D = 2 L + 3 (1 + 2
+// bands) <= 64).  No packing: the lookups gather straight from the table, and every block
+// stages the MLP (transposed, one row per input) in LDS.
+//
+// Query: one ray per thread; the 8 L corner gathers are the traffic (random 8-byte reads of
+// a 52 MB table that the 256 MB Infinity Cache holds); the MLP is fp32 FMA with the weights
+// broadcast from LDS.  Training: the same forward writes the logits; the backward kernel
+// re-runs it per ray, keeps the layer inputs and deltas for the weight-gradient reduction
+// (fixed order), and scatters the position-code gradient into the table gradient with
+// float atomics (the one reduction here whose order is not fixed).
+#include <math.h>
+
+#include <algorithm>
+
+#include "ddf_internal.h"
+#include "ddf_train.h"
+
+namespace ddf {
+
+namespace {
+
+constexpr int kHMaxLevels = 24;
+constexpr int kHW = 64;           // MLP width
+constexpr int kHIn = 64;          // padded MLP input
+constexpr int kHMaxHidden = 2;   // the compiled kernels run two hidden layers
+constexpr int kHT = 256;          // threads per block, one ray each
+constexpr int kHRC = 64;          // rays per weight-gradient block
+constexpr uint32_t kPrime1 = 2654435761u, kPrime2 = 805459861u;
+
+struct HashLayout {
+  int n_levels, d_in, n_dir, n_hidden, n_out, dir_bands;
+  int res[kHMaxLevels];
+  int dense[kHMaxLevels];
+  int64_t off[kHMaxLevels];       // entry offset of each level
+  uint32_t tmask;                 // entries per hashed level - 1
+  int64_t entries;                // all table entries
+  int64_t w_off[kHMaxHidden + 1], b_off[kHMaxHidden + 1];   // float offsets, heads last
+  int64_t wh_off, bh_off;         // the heads' offsets again (read on the device without an index)
+  int64_t params;
+  float box_half;
+};
+
+HashLayout make_hash_layout(const ddf_hash_desc& d) {
+  HashLayout L{};
+  L.n_levels = d.n_levels;
+  L.dir_bands = d.dir_bands;
+  L.n_dir = 3 * (1 + 2 * d.dir_bands);
+  L.d_in = 2 * d.n_levels + L.n_dir;
+  L.n_hidden = d.n_hidden;
+  L.n_out = d.n_out;
+  L.box_half = d.box_half;
+  const int64_t T = 1ll << d.log2_table;
+  L.tmask = (uint32_t)(T - 1);
+  int64_t off = 0;
+  for (int l = 0; l < d.n_levels; ++l) {
+    const int N = (int)floor((double)d.base_res * pow((double)d.growth, (double)l));
+    const int64_t full = (int64_t)(N + 1) * (N + 1) * (N + 1);
+    L.res[l] = N;
+    L.dense[l] = full <= T;
+    L.off[l] = off;
+    off += full <= T ? full : T;
+  }
+  L.entries = off;
+  int64_t p = 2 * off;
+  int fan_in = L.d_in;
+  for (int l = 0; l <= d.n_hidden; ++l) {
+    const int o = l < d.n_hidden ? kHW : d.n_out;
+    L.w_off[l] = p; p += (int64_t)o * fan_in;
+    L.b_off[l] = p; p += o;
+    fan_in = o;
+  }
+  L.params = p;
+  L.wh_off = L.w_off[d.n_hidden];
+  L.bh_off = L.b_off[d.n_hidden];
+  return L;
+}
+
+bool hash_shape_supported(int nl, int nb, int nh);
+
+int check_hash_desc(const ddf_hash_desc* d) {
+  if (!d) return fail(DDF_ERR_INVALID_ARG, "desc is NULL");
+  if (d->n_feat != 2) return fail(DDF_ERR_UNSUPPORTED, "n_feat must be 2");
+  if (d->width != kHW) return fail(DDF_ERR_UNSUPPORTED, "width must be 64");
+  if (d->n_hidden != kHMaxHidden) return fail(DDF_ERR_UNSUPPORTED, "n_hidden must be 2");
+  if (d->n_out != 2) return fail(DDF_ERR_UNSUPPORTED, "n_out must be 2 (t, xi)");
+  if (d->n_levels < 1 || d->n_levels > kHMaxLevels) return fail(DDF_ERR_UNSUPPORTED, "n_levels must be 1..24");
+  if (d->log2_table < 4 || d->log2_table > 24) return fail(DDF_ERR_UNSUPPORTED, "log2_table must be 4..24");
+  if (d->dir_bands < 0 || 2 * d->n_levels + 3 * (1 + 2 * d->dir_bands) > kHIn)
+    return fail(DDF_ERR_UNSUPPORTED, "2 n_levels + 3 (1 + 2 dir_bands) must be <= 64");
+  if (d->base_res < 1 || !(d->growth >= 1.f && d->growth <= 8.f) || !(d->box_half > 0.f))
+    return fail(DDF_ERR_INVALID_ARG, "base_res, growth or box_half out of range");
+  if (!hash_shape_supported(d->n_levels, d->dir_bands, d->n_hidden))
+    return fail(DDF_ERR_UNSUPPORTED, "compiled shapes: 16 or 6 levels, 4 direction bands, 2 hidden layers");
+  const double top = (double)d->base_res * pow((double)d->growth, (double)(d->n_levels - 1));
+  if (!(top < 1.0e6)) return fail(DDF_ERR_UNSUPPORTED, "finest resolution must stay below 1e6");
+  return DDF_OK;
+}
+
+// The MLP staged in LDS: every layer transposed (row i = the weights of input i into the 64
+// outputs, zero rows past the input width), the heads row-major, the biases.
+struct HashSmem {
+  float wt[kHMaxHidden][kHIn][kHW];
+  float b[kHMaxHidden][kHW];
+  float wh[2][kHW];
+  float bh[2];
+};
+
+__device__ __forceinline__ void stage_mlp(const HashLayout& L, const float* __restrict__ params, HashSmem& s) {
+#pragma unroll
+  for (int l = 0; l < kHMaxHidden; ++l) {   // static indices into the argument block
+    if (l >= L.n_hidden) break;
+    const int fan_in = l == 0 ? L.d_in : kHW;
+    const float* W = params + L.w_off[l];
+    for (int k = threadIdx.x; k < kHIn * kHW; k += blockDim.x) {
+      const int i = k / kHW, j = k % kHW;
+      s.wt[l][i][j] = i < fan_in ? W[(int64_t)j * fan_in + i] : 0.f;
+    }
+    for (int j = threadIdx.x; j < kHW; j += blockDim.x) s.b[l][j] = params[L.b_off[l] + j];
+  }
+  for (int k = threadIdx.x; k < 2 * kHW; k += blockDim.x) s.wh[k / kHW][k % kHW] = params[L.wh_off + k];
+  if (threadIdx.x < 2) s.bh[threadIdx.x] = params[L.bh_off + threadIdx.x];
+}
+
+// The per-level lookup constants, staged in LDS so that no helper holds a reference to the
+// kernel's argument block (which would force a private copy of it).
+struct LevelTab {
+  int res[kHMaxLevels];
+  int dense[kHMaxLevels];
+  int64_t off[kHMaxLevels];
+  uint32_t tmask;
+  float box_half;
+};
+
+__device__ __forceinline__ void stage_levels(const HashLayout& L, LevelTab& t) {
+  if (threadIdx.x < kHMaxLevels) {
+    t.res[threadIdx.x] = L.res[threadIdx.x];
+    t.dense[threadIdx.x] = L.dense[threadIdx.x];
+    t.off[threadIdx.x] = L.off[threadIdx.x];
+  }
+  if (threadIdx.x == 0) {
+    t.tmask = L.tmask;
+    t.box_half = L.box_half;
+  }
+}
+
+// Cell of point p (unit cube) at level l: lower vertex c and weights w.
+__device__ __forceinline__ void cell(float N, const float (&p)[3], uint32_t (&c)[3], float (&w)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float sv = p[a] * N;
+    const float fl = fminf(floorf(sv), N - 1.f);
+    w[a] = sv - fl;
+    c[a] = (uint32_t)fl;
+  }
+}
+
+// Table entry and trilinear weight of corner k (bit a of k: +1 along axis a).
+__device__ __forceinline__ void corner(const LevelTab& L, int l, const uint32_t (&c)[3], const float (&w)[3], int k,
+                              int64_t& entry, float& wt) {
+  const uint32_t v0 = c[0] + (k & 1), v1 = c[1] + ((k >> 1) & 1), v2 = c[2] + ((k >> 2) & 1);
+  const uint32_t n1 = (uint32_t)L.res[l] + 1u;
+  const uint32_t idx = L.dense[l] ? v0 + n1 * (v1 + n1 * v2) : ((v0 ^ (v1 * kPrime1) ^ (v2 * kPrime2)) & L.tmask);
+  entry = L.off[l] + idx;
+  wt = ((k & 1) ? w[0] : 1.f - w[0]) * (((k >> 1) & 1) ? w[1] : 1.f - w[1]) * (((k >> 2) & 1) ? w[2] : 1.f - w[2]);
+}
+
+__device__ __forceinline__ void unit_point(const LevelTab& L, const float (&x)[3], float (&p)[3]) {
+  const float inv = 0.5f / L.box_half;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) p[a] = fminf(fmaxf((x[a] + L.box_half) * inv, 0.f), 1.f);
+}
+
+// h[j] += row[j] v for the 64 outputs (row: one input's weights, LDS).
+__device__ __forceinline__ void axpy_row(const float* row, float v, float (&h)[kHW]) {
+  const f32x4* r4 = reinterpret_cast<const f32x4*>(row);
+#pragma unroll
+  for (int q = 0; q < kHW / 4; ++q) {
+    const f32x4 w4 = r4[q];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) h[4 * q + e] = fmaf(w4[e], v, h[4 * q + e]);
+  }
+}
+
+// sum_j row[j] v[j].
+__device__ __forceinline__ float dot_row(const float* row, const float (&v)[kHW]) {
+  const f32x4* r4 = reinterpret_cast<const f32x4*>(row);
+  float acc = 0.f;
+#pragma unroll
+  for (int q = 0; q < kHW / 4; ++q) {
+    const f32x4 w4 = r4[q];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc = fmaf(w4[e], v[4 * q + e], acc);
+  }
+  return acc;
+}
+
+// The first layer's pre-activation of one ray, fused with the encoding: each input feature
+// is added into h = b1 + W1 g as soon as it exists, so the 64-wide input vector is never held.
+// Features in order: the trilinear lookup of every level (2 each), then the direction code
+// [d, sin(pi 2^k d), cos(pi 2^k d)]_{k < NB}.  With `keep`, every feature is also stored to
+// keep[i] (the backward pass's copy of the layer input, 64 floats per ray).  Two levels' gathers are in
+// flight at a time.
+template <int NL, int NB>
+__device__ __forceinline__ void encode_layer1(const LevelTab& L, const HashSmem& s, const float* __restrict__ table,
+                                     const float (&x)[3], const float (&dv)[3], float (&h)[kHW], float* keep) {
+#pragma unroll
+  for (int j = 0; j < kHW; ++j) h[j] = s.b[0][j];
+  float p[3];
+  unit_point(L, x, p);
+  const float2* tab = reinterpret_cast<const float2*>(table);
+  float f[2 * NL];   // the lookups first (all gathers in flight together), then the products
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    uint32_t c[3];
+    float w[3];
+    cell((float)L.res[l], p, c, w);
+    float f0 = 0.f, f1 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int64_t e;
+      float wt;
+      corner(L, l, c, w, k, e, wt);
+      const float2 t = tab[e];
+      f0 = fmaf(wt, t.x, f0);
+      f1 = fmaf(wt, t.y, f1);
+    }
+    f[2 * l] = f0;
+    f[2 * l + 1] = f1;
+    if ((l & 3) == 3) __builtin_amdgcn_sched_barrier(0);   // at most 4 levels of gathers in flight
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int i = 0; i < 2 * NL; ++i) {
+    axpy_row(s.wt[0][i], f[i], h);
+    if (keep) keep[i] = f[i];
+    if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+  constexpr int D0 = 2 * NL;
+#pragma unroll
+  for (int k = -1; k < NB; ++k)
+#pragma unroll
+    for (int part = 0; part < (k < 0 ? 1 : 2); ++part)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        float v;
+        if (k < 0) {
+          v = dv[a];
+        } else {
+          float sn, cs;
+          sincospif(ldexpf(dv[a], k), &sn, &cs);
+          v = part == 0 ? sn : cs;
+        }
+        const int i = k < 0 ? D0 + a : D0 + 3 + 6 * k + 3 * part + a;
+        axpy_row(s.wt[0][i], v, h);
+        if (keep) keep[i] = v;
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  if (keep) {
+#pragma unroll
+    for (int i = D0 + 3 * (1 + 2 * NB); i < kHIn; ++i) keep[i] = 0.f;
+  }
+}
+
+// out = ReLU(b + W in) for a square hidden layer (weights transposed in LDS).
+__device__ __forceinline__ void hidden_relu(const float (&wt)[kHIn][kHW], const float (&b)[kHW], const float (&in)[kHW],
+                                   float (&out)[kHW]) {
+#pragma unroll
+  for (int j = 0; j < kHW; ++j) out[j] = b[j];
+#pragma unroll
+  for (int i = 0; i < kHW; ++i) {
+    axpy_row(wt[i], in[i], out);
+    if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int j = 0; j < kHW; ++j) out[j] = fmaxf(out[j], 0.f);
+}
+
+struct HashArgs {
+  HashLayout L;
+  const float* params;
+  const float* rays;      // [6][n]
+  int64_t n;
+  int mode;               // 0: t, xi   1: logits
+  float* out0;
+  float* out1;
+  // backward
+  const float* dzt;
+  const float* dzx;
+  float* acts;            // [n_hidden + 1][R][64]: the input code, then each hidden layer's output
+  float* deltas;          // [n_hidden][R][64]: dL/da of each hidden layer
+  float* gtab;            // table gradient [entries][2] (atomics)
+  int64_t R;
+};
+
+template <int NL, int NB, int NH>
+__global__ __launch_bounds__(kHT) void hash_fwd_kernel(HashArgs a) {
+  __shared__ __attribute__((aligned(16))) HashSmem s;
+  __shared__ LevelTab lt;
+  stage_mlp(a.L, a.params, s);
+  stage_levels(a.L, lt);
+  __syncthreads();
+  // one ray per thread and no loop over rays: the weights read from LDS are then not
+  // loop-invariant, so they are never hoisted into registers
+  {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n) return;
+    float x[3], dv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { x[c] = a.rays[c * a.n + r]; dv[c] = a.rays[(3 + c) * a.n + r]; }
+    float h[kHW], h2[kHW];
+    encode_layer1<NL, NB>(lt, s, a.params, x, dv, h2, nullptr);
+#pragma unroll
+    for (int j = 0; j < kHW; ++j) h[j] = fmaxf(h2[j], 0.f);
+#pragma unroll
+    for (int l = 1; l < NH; ++l) {
+      hidden_relu(s.wt[l], s.b[l], h, h2);
+#pragma unroll
+      for (int j = 0; j < kHW; ++j) h[j] = h2[j];
+    }
+    float z0 = s.bh[0], z1 = s.bh[1];
+#pragma unroll
+    for (int j = 0; j < kHW; ++j) {
+      z0 = fmaf(s.wh[0][j], h[j], z0);
+      z1 = fmaf(s.wh[1][j], h[j], z1);
+    }
+    if (a.mode == 0) {
+      a.out0[r] = softplusf_(z0);
+      a.out1[r] = sigmoidf_(z1);
+    } else {
+      a.out0[r] = z0;
+      a.out1[r] = z1;
+    }
+  }
+}
+
+__device__ inline void store_row(float* dst, const float (&v)[kHW]) {
+  f32x4* d4 = reinterpret_cast<f32x4*>(dst);
+#pragma unroll
+  for (int q = 0; q < kHW / 4; ++q) d4[q] = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+}
+
+// ---- training: one simple kernel per stage, activations in memory ([R][64] per layer)
+
+// The input code of every ray (rows n .. R - 1: the code of the box centre, zero direction).
+template <int NL, int NB>
+__global__ __launch_bounds__(kHT) void hash_encode_kernel(HashArgs a) {
+  __shared__ LevelTab lt;
+  stage_levels(a.L, lt);
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.R) return;
+  float x[3] = {0.f, 0.f, 0.f}, dv[3] = {0.f, 0.f, 0.f};
+  if (r < a.n) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { x[c] = a.rays[c * a.n + r]; dv[c] = a.rays[(3 + c) * a.n + r]; }
+  }
+  float p[3];
+  unit_point(lt, x, p);
+  const float2* tab = reinterpret_cast<const float2*>(a.params);
+  float g[kHIn];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    uint32_t c[3];
+    float w[3];
+    cell((float)lt.res[l], p, c, w);
+    float f0 = 0.f, f1 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int64_t e;
+      float wt;
+      corner(lt, l, c, w, k, e, wt);
+      const float2 t = tab[e];
+      f0 = fmaf(wt, t.x, f0);
+      f1 = fmaf(wt, t.y, f1);
+    }
+    g[2 * l] = f0;
+    g[2 * l + 1] = f1;
+  }
+  constexpr int D0 = 2 * NL;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) g[D0 + q] = dv[q];
+#pragma unroll
+  for (int k = 0; k < NB; ++k)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      float sn, cs;
+      sincospif(ldexpf(dv[q], k), &sn, &cs);
+      g[D0 + 3 + 6 * k + q] = sn;
+      g[D0 + 6 + 6 * k + q] = cs;
+    }
+#pragma unroll
+  for (int i = D0 + 3 * (1 + 2 * NB); i < kHIn; ++i) g[i] = 0.f;
+  f32x4* dst = reinterpret_cast<f32x4*>(a.acts + r * kHIn);
+#pragma unroll
+  for (int q = 0; q < kHIn / 4; ++q) dst[q] = f32x4{g[4 * q], g[4 * q + 1], g[4 * q + 2], g[4 * q + 3]};
+}
+
+// out[r][o] = act(b[o] + sum_i W[o][i] in[r][i]) for O <= 64 outputs (W [O][fan_in], master
+// layout); act = ReLU, or none for the heads, whose two logits go to out0 / out1.
+__global__ __launch_bounds__(kHT) void dense_fwd_kernel(const float* in, const float* W, const float* b, int O,
+                                                        int fan_in, int64_t R, int relu, float* out, float* out0,
+                                                        float* out1) {
+  __shared__ __attribute__((aligned(16))) float wt[kHIn][kHW];   // transposed, zero padded
+  __shared__ float bs[kHW];
+  for (int k = threadIdx.x; k < kHIn * kHW; k += blockDim.x) {
+    const int i = k / kHW, o = k % kHW;
+    wt[i][o] = (i < fan_in && o < O) ? W[(int64_t)o * fan_in + i] : 0.f;
+  }
+  for (int o = threadIdx.x; o < kHW; o += blockDim.x) bs[o] = o < O ? b[o] : 0.f;
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  float acc[kHW];
+#pragma unroll
+  for (int o = 0; o < kHW; ++o) acc[o] = bs[o];
+  const f32x4* src = reinterpret_cast<const f32x4*>(in + r * kHIn);
+  for (int q = 0; q < kHIn / 4; ++q) {
+    const f32x4 x4 = src[q];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) axpy_row(wt[4 * q + e], x4[e], acc);
+  }
+  if (out) {
+#pragma unroll
+    for (int o = 0; o < kHW; ++o) acc[o] = relu ? fmaxf(acc[o], 0.f) : acc[o];
+    store_row(out + r * kHW, acc);
+  } else {
+    out0[r] = acc[0];
+    out1[r] = acc[1];
+  }
+}
+
+// d_in[r][i] = mask(in[r][i] > 0) sum_o W[o][i] d_out[r][o] for the hidden layers (W [O][fan_in]
+// master layout, d_out [R][64]); `mask_src` null: no mask.  With dz0 / dz1 set, d_out is the
+// pair of logit gradients instead (the heads).
+__global__ __launch_bounds__(kHT) void dense_bwd_kernel(const float* d_out, const float* dz0, const float* dz1,
+                                                        const float* W, int O, int fan_in, int64_t R,
+                                                        const float* mask_src, float* d_in) {
+  __shared__ __attribute__((aligned(16))) float wr[kHW][kHIn];   // rows of W, zero padded
+  for (int k = threadIdx.x; k < kHW * kHIn; k += blockDim.x) {
+    const int o = k / kHIn, i = k % kHIn;
+    wr[o][i] = (o < O && i < fan_in) ? W[(int64_t)o * fan_in + i] : 0.f;
+  }
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  float acc[kHIn];
+#pragma unroll
+  for (int i = 0; i < kHIn; ++i) acc[i] = 0.f;
+  if (dz0) {
+    axpy_row(wr[0], dz0[r], acc);
+    axpy_row(wr[1], dz1[r], acc);
+  } else {
+    const f32x4* src = reinterpret_cast<const f32x4*>(d_out + r * kHW);
+    for (int q = 0; q < kHW / 4; ++q) {
+      const f32x4 d4 = src[q];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) axpy_row(wr[4 * q + e], d4[e], acc);
+    }
+  }
+  if (mask_src) {
+    const f32x4* m4 = reinterpret_cast<const f32x4*>(mask_src + r * kHIn);
+#pragma unroll
+    for (int q = 0; q < kHIn / 4; ++q) {
+      const f32x4 h4 = m4[q];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[4 * q + e] = h4[e] > 0.f ? acc[4 * q + e] : 0.f;
+    }
+  }
+  store_row(d_in + r * kHIn, acc);
+}
+
+// The position-code gradient dg [R][64] (first 2 NL entries) of every live ray scattered to
+// the 8 corners of every level with the lookup weights (float atomics).
+template <int NL>
+__global__ __launch_bounds__(kHT) void hash_scatter_kernel(HashArgs a, const float* dg) {
+  __shared__ LevelTab lt;
+  stage_levels(a.L, lt);
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n) return;
+  float x[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x[c] = a.rays[c * a.n + r];
+  float p[3];
+  unit_point(lt, x, p);
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    const float2 gl = *reinterpret_cast<const float2*>(dg + r * kHIn + 2 * l);
+    uint32_t c[3];
+    float w[3];
+    cell((float)lt.res[l], p, c, w);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int64_t e;
+      float wt;
+      corner(lt, l, c, w, k, e, wt);
+      atomicAdd(a.gtab + 2 * e, wt * gl.x);
+      atomicAdd(a.gtab + 2 * e + 1, wt * gl.y);
+    }
+  }
+}
+
+// part[blk][o I + i] = sum over the block's rays of d[r][o] a[r][i]; part[blk][O I + o] =
+// sum of d[r][o] (bias), for ray-major d [R][ldd] (first O columns) and a [R][64].  Fixed order.
+__global__ __launch_bounds__(kHT) void outer_reduce_kernel(const float* d, int ldd, const float* a, int O, int I,
+                                                           float* part) {
+  __shared__ float sd[kHRC][kHW + 1], sa[kHRC][kHIn + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * kHRC;
+  for (int k = threadIdx.x; k < kHRC * O; k += blockDim.x) sd[k / O][k % O] = d[(r0 + k / O) * ldd + k % O];
+  for (int k = threadIdx.x; k < kHRC * I; k += blockDim.x) sa[k / I][k % I] = a[(r0 + k / I) * kHIn + k % I];
+  __syncthreads();
+  const int nout = O * I + O;
+  float* dst = part + (int64_t)blockIdx.x * nout;
+  for (int k = threadIdx.x; k < nout; k += blockDim.x) {
+    float acc = 0.f;
+    if (k < O * I) {
+      const int o = k / I, i = k % I;
+      for (int r = 0; r < kHRC; ++r) acc = fmaf(sd[r][o], sa[r][i], acc);
+    } else {
+      const int o = k - O * I;
+      for (int r = 0; r < kHRC; ++r) acc += sd[r][o];
+    }
+    dst[k] = acc;
+  }
+}
+
+// out[k] = sum over blocks b (in order) of part[b][k].
+__global__ void sum_parts_kernel(const float* part, int nblk, int stride, float* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= stride) return;
+  float s = 0.f;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * stride + k];
+  out[k] = s;
+}
+
+__global__ void fill_zero_kernel(float* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.f;
+}
+
+// Weight-gradient rows of a layer in the master layout: W [o][fan_in] then b [o].
+__global__ void scatter_layer_grad_kernel(const float* src /*[O*I + O], inputs padded to I*/, int O, int I, int fan_in,
+                                          float* w, float* b) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < O * fan_in) {
+    const int o = k / fan_in, i = k % fan_in;
+    w[k] = src[o * I + i];
+  } else if (k < O * fan_in + O) {
+    b[k - O * fan_in] = src[O * I + (k - O * fan_in)];
+  }
+}
+
+struct HashWs {
+  int64_t R;
+  int64_t zt, zx, dzt, dzx, lossp, scal, acts, deltas, part, layer, grad, total;
+};
+
+HashWs hash_ws(const HashLayout& L, int64_t batch) {
+  HashWs w{};
+  w.R = (batch + kHRC - 1) / kHRC * kHRC;
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) { const int64_t o = off; off = align256(off + bytes); return o; };
+  w.zt = take(4 * w.R); w.zx = take(4 * w.R); w.dzt = take(4 * w.R); w.dzx = take(4 * w.R);
+  w.lossp = take(4ll * loss_scratch_floats());
+  w.scal = take(64);
+  w.acts = take(4ll * 3 * kHIn * w.R);     // G, H1, H2
+  w.deltas = take(4ll * 3 * kHIn * w.R);   // D2, D1, DG
+  w.part = take(4ll * (w.R / kHRC) * (kHW * kHIn + kHW));
+  w.layer = take(4ll * (kHW * kHIn + kHW));
+  w.grad = take(4 * L.params);
+  w.total = off;
+  return w;
+}
+
+// Encodings with a compiled kernel: (levels, direction bands).
+bool hash_shape_supported(int nl, int nb, int nh) { return (nl == 16 || nl == 6) && nb == 4 && nh == 2; }
+
+int run_hash_forward(const HashLayout& L, const float* params, const float* rays, int64_t n, int mode, float* o0,
+                     float* o1, hipStream_t st) {
+  HashArgs a{};
+  a.L = L; a.params = params; a.rays = rays; a.n = n; a.mode = mode; a.out0 = o0; a.out1 = o1;
+  const unsigned blocks = (unsigned)((n + kHT - 1) / kHT);
+  if (L.n_levels == 16)
+    hash_fwd_kernel<16, 4, 2><<<blocks, kHT, 0, st>>>(a);
+  else
+    hash_fwd_kernel<6, 4, 2><<<blocks, kHT, 0, st>>>(a);
+  return hip_status(hipGetLastError(), "hash forward launch");
+}
+
+// The training pass after the forward (stages in memory, [R][64] per layer, R a multiple of
+// 64): G = code, H1, H2; D2, D1, DG the deltas and the code gradient.
+int run_hash_encode(const HashArgs& a, hipStream_t st) {
+  const unsigned blocks = (unsigned)((a.R + kHT - 1) / kHT);
+  if (a.L.n_levels == 16)
+    hash_encode_kernel<16, 4><<<blocks, kHT, 0, st>>>(a);
+  else
+    hash_encode_kernel<6, 4><<<blocks, kHT, 0, st>>>(a);
+  return hip_status(hipGetLastError(), "hash encode launch");
+}
+
+int run_hash_scatter(const HashArgs& a, const float* dg, hipStream_t st) {
+  const unsigned blocks = (unsigned)((a.n + kHT - 1) / kHT);
+  if (a.L.n_levels == 16)
+    hash_scatter_kernel<16><<<blocks, kHT, 0, st>>>(a, dg);
+  else
+    hash_scatter_kernel<6><<<blocks, kHT, 0, st>>>(a, dg);
+  return hip_status(hipGetLastError(), "hash scatter launch");
+}
+
+}  // namespace
+
+}  // namespace ddf
+
+using namespace ddf;
+
+extern "C" {
+
+size_t ddf_hash_param_count(const ddf_hash_desc* d) {
+  if (check_hash_desc(d) != DDF_OK) return 0;
+  return (size_t)make_hash_layout(*d).params;
+}
+
+int ddf_hash_level(const ddf_hash_desc* d, int32_t level, int32_t* resolution, int64_t* entries, int64_t* offset,
+                   int32_t* hashed) {
+  int rc;
+  if ((rc = check_hash_desc(d))) return rc;
+  if (level < 0 || level >= d->n_levels) return fail(DDF_ERR_INVALID_ARG, "level %d out of range", level);
+  const HashLayout L = make_hash_layout(*d);
+  const int64_t T = 1ll << d->log2_table;
+  if (resolution) *resolution = L.res[level];
+  if (entries) *entries = L.dense[level] ? (int64_t)(L.res[level] + 1) * (L.res[level] + 1) * (L.res[level] + 1) : T;
+  if (offset) *offset = L.off[level];
+  if (hashed) *hashed = !L.dense[level];
+  return DDF_OK;
+}
+
+int ddf_hash_query(const ddf_hash_desc* d, const float* params, const float* rays, int64_t n, float* t, float* xi,
+                   void* stream) {
+  int rc;
+  if ((rc = check_hash_desc(d))) return rc;
+  if (n < 0 || n > (int64_t)INT32_MAX) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(params, "params")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(t, "t")) ||
+      (rc = check_ptr(xi, "xi")))
+    return rc;
+  g_err_clear();
+  return run_hash_forward(make_hash_layout(*d), params, rays, n, 0, t, xi, (hipStream_t)stream);
+}
+
+size_t ddf_hash_train_workspace_bytes(const ddf_hash_desc* d, int64_t batch) {
+  if (check_hash_desc(d) != DDF_OK || batch < 0) return 0;
+  return (size_t)hash_ws(make_hash_layout(*d), batch).total;
+}
+
+int ddf_hash_train_step(const ddf_hash_desc* d, float* params, float* adam_m, float* adam_v, const float* rays,
+                        const float* t_gt, const uint8_t* hit_gt, int64_t batch, const ddf_train_hparams* hp,
+                        float* loss_out, int32_t* nonfinite_flag, float* grad_out, void* ws, size_t ws_bytes,
+                        void* stream) {
+  int rc;
+  if ((rc = check_hash_desc(d)) || (rc = check_hp_public(hp))) return rc;
+  if (!(hp->l1_clamp > 0.f) || !(hp->bce_weight >= 0.f))
+    return fail(DDF_ERR_INVALID_ARG, "loss hyper-parameters out of range");
+  if (batch < 1 || batch > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "batch = %lld out of range", (long long)batch);
+  if ((rc = check_ptr(params, "params")) || (rc = check_ptr(adam_m, "adam_m")) || (rc = check_ptr(adam_v, "adam_v")) ||
+      (rc = check_ptr(rays, "rays")) || (rc = check_ptr(t_gt, "t_gt")) || (rc = check_ptr(hit_gt, "hit_gt")) ||
+      (rc = check_ptr(loss_out, "loss_out")) || (rc = check_ptr(nonfinite_flag, "nonfinite_flag")) ||
+      (rc = check_ptr(ws, "ws")))
+    return rc;
+  if (grad_out && (rc = check_ptr(grad_out, "grad_out"))) return rc;
+  const HashLayout L = make_hash_layout(*d);
+  const HashWs w = hash_ws(L, batch);
+  if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t* wb = static_cast<uint8_t*>(ws);
+  float* zt = reinterpret_cast<float*>(wb + w.zt);
+  float* zx = reinterpret_cast<float*>(wb + w.zx);
+  float* dzt = reinterpret_cast<float*>(wb + w.dzt);
+  float* dzx = reinterpret_cast<float*>(wb + w.dzx);
+  float* grad = grad_out ? grad_out : reinterpret_cast<float*>(wb + w.grad);
+  g_err_clear();
+  HashArgs a{};
+  a.L = L; a.params = params; a.rays = rays; a.n = batch; a.R = w.R;
+  float* acts = reinterpret_cast<float*>(wb + w.acts);
+  float* G = acts;
+  float* H1 = acts + w.R * kHIn;
+  float* H2 = acts + 2 * w.R * kHIn;
+  float* dl = reinterpret_cast<float*>(wb + w.deltas);
+  float* D2 = dl;
+  float* D1 = dl + w.R * kHIn;
+  float* DG = dl + 2 * w.R * kHIn;
+  a.acts = G;
+  a.gtab = grad;
+  const unsigned rb = (unsigned)((w.R + kHT - 1) / kHT);
+  const float* P = params;
+  // forward through memory
+  if ((rc = run_hash_encode(a, st))) return rc;
+  dense_fwd_kernel<<<rb, kHT, 0, st>>>(G, P + L.w_off[0], P + L.b_off[0], kHW, L.d_in, w.R, 1, H1, nullptr, nullptr);
+  dense_fwd_kernel<<<rb, kHT, 0, st>>>(H1, P + L.w_off[1], P + L.b_off[1], kHW, kHW, w.R, 1, H2, nullptr, nullptr);
+  dense_fwd_kernel<<<rb, kHT, 0, st>>>(H2, P + L.wh_off, P + L.bh_off, 2, kHW, w.R, 0, nullptr, zt, zx);
+  if ((rc = hip_status(hipGetLastError(), "hash training forward launch"))) return rc;
+  if ((rc = launch_ddf_loss(zt, zx, t_gt, hit_gt, batch, w.R, reinterpret_cast<float*>(wb + w.lossp),
+                            reinterpret_cast<float*>(wb + w.scal), loss_out, dzt, dzx, hp->bce_weight, hp->l1_clamp, st)))
+    return rc;
+  // backward: deltas, then the code gradient, its scatter into the table, the weight gradients
+  dense_bwd_kernel<<<rb, kHT, 0, st>>>(nullptr, dzt, dzx, P + L.wh_off, 2, kHW, w.R, H2, D2);
+  dense_bwd_kernel<<<rb, kHT, 0, st>>>(D2, nullptr, nullptr, P + L.w_off[1], kHW, kHW, w.R, H1, D1);
+  dense_bwd_kernel<<<rb, kHT, 0, st>>>(D1, nullptr, nullptr, P + L.w_off[0], kHW, L.d_in, w.R, nullptr, DG);
+  fill_zero_kernel<<<1024, 256, 0, st>>>(grad, 2 * L.entries);
+  if ((rc = hip_status(hipGetLastError(), "hash backward launch"))) return rc;
+  if ((rc = run_hash_scatter(a, DG, st))) return rc;
+  const unsigned nblk = (unsigned)(w.R / kHRC);
+  float* part = reinterpret_cast<float*>(wb + w.part);
+  float* layer = reinterpret_cast<float*>(wb + w.layer);
+  const float* din[2] = {D1, D2};
+  const float* ain[2] = {G, H1};
+  for (int l = 0; l < 2; ++l) {
+    const int fan_in = l == 0 ? L.d_in : kHW;
+    outer_reduce_kernel<<<nblk, kHT, 0, st>>>(din[l], kHW, ain[l], kHW, kHIn, part);
+    sum_parts_kernel<<<(unsigned)((kHW * kHIn + kHW + 255) / 256), 256, 0, st>>>(part, (int)nblk, kHW * kHIn + kHW, layer);
+    scatter_layer_grad_kernel<<<(unsigned)((kHW * fan_in + kHW + 255) / 256), 256, 0, st>>>(
+        layer, kHW, kHIn, fan_in, grad + L.w_off[l], grad + L.b_off[l]);
+  }
+  for (int o = 0; o < 2; ++o) {   // the heads: each logit gradient against H2
+    outer_reduce_kernel<<<nblk, kHT, 0, st>>>(o == 0 ? dzt : dzx, 1, H2, 1, kHIn, part);
+    sum_parts_kernel<<<(unsigned)((kHIn + 1 + 255) / 256), 256, 0, st>>>(part, (int)nblk, kHIn + 1, layer);
+    scatter_layer_grad_kernel<<<1, 256, 0, st>>>(layer, 1, kHIn, kHW, grad + L.wh_off + o * kHW, grad + L.bh_off + o);
+  }
+  if ((rc = hip_status(hipGetLastError(), "hash weight-gradient launch"))) return rc;
+  return launch_adam_flat(params, adam_m, adam_v, grad, L.params, hp, nonfinite_flag, st);
+}
+
+}  // extern "C"

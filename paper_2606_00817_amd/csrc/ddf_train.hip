@@ -639,6 +639,8 @@ static int check_hp(const ddf_train_hparams* hp) {
   return DDF_OK;
 }
 
+int check_hp_public(const ddf_train_hparams* hp) { return check_hp(hp); }
+
 // Adam on the fp32 master (skipped as a whole when any gradient is not finite), then the
 // repack of the working copy.
 static int run_adam(const ddf_net_desc& d, float* master, float* adam_m, float* adam_v, void* packed,
@@ -792,6 +794,35 @@ static int run_forward_train(const ddf_net_desc& d, const void* packed, const fl
   const TrainPtrs p = train_ptrs(d, w, ws);
   return run_forward_rows(d, packed, rays, n, zt, zx, w, p, 0, d.n_hidden, st);
 }
+
+// The distillation loss over logits already in device memory: the three terms into loss_out
+// and the per-ray logit gradients into dzt / dzx (rows n .. R - 1 zero).  Scratch: partial
+// (kLossBlocks x 8 floats) and scal (64 bytes).  Used by the hash-grid field as well.
+int launch_ddf_loss(const float* zt, const float* zx, const float* t_gt, const uint8_t* hit, int64_t n, int64_t R,
+                    float* partial, float* scal, float* loss_out, float* dzt, float* dzx, float bce_weight,
+                    float clamp, hipStream_t st) {
+  LossArgs la{};
+  la.zt = zt; la.zx = zx; la.tgt = t_gt; la.hit = hit; la.n = n; la.R = R;
+  la.partial = partial; la.scal = scal; la.loss_out = loss_out; la.dzt = dzt; la.dzx = dzx;
+  la.bce_weight = bce_weight; la.clamp = clamp;
+  loss_partial_kernel<<<kLossBlocks, kThreads, 0, st>>>(la);
+  loss_final_kernel<<<1, 64, 0, st>>>(la);
+  loss_grad_kernel<<<(unsigned)((R + 255) / 256), 256, 0, st>>>(la);
+  return hip_status(hipGetLastError(), "loss launch");
+}
+
+// Adam over a flat fp32 parameter vector (skipped as a whole on a non-finite gradient).
+int launch_adam_flat(float* p, float* m, float* v, const float* g, int64_t P, const ddf_train_hparams* hp,
+                     int32_t* flag, hipStream_t st) {
+  zero_flag_kernel<<<1, 64, 0, st>>>(flag);
+  finite_check_kernel<<<1024, 256, 0, st>>>(g, P, flag);
+  const double bc1 = 1.0 - pow((double)hp->beta1, (double)hp->step);
+  const double bc2 = 1.0 - pow((double)hp->beta2, (double)hp->step);
+  adam_kernel<<<2048, 256, 0, st>>>(p, m, v, g, P, flag, hp->lr, hp->beta1, hp->beta2, hp->eps, (float)bc1, (float)bc2);
+  return hip_status(hipGetLastError(), "adam launch");
+}
+
+int loss_scratch_floats() { return 8 * kLossBlocks; }
 
 static int check_recompute(int recompute_every) {
   if (recompute_every < 0) return fail(DDF_ERR_INVALID_ARG, "recompute_every = %d must be >= 0", recompute_every);

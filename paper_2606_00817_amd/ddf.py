@@ -35,6 +35,13 @@ class TrainHParamsC(ctypes.Structure):
                 ("step", ctypes.c_int64), ("recompute_every", ctypes.c_int32)]
 
 
+class HashDescC(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("n_feat", ctypes.c_int32), ("log2_table", ctypes.c_int32),
+                ("base_res", ctypes.c_int32), ("growth", ctypes.c_float), ("dir_bands", ctypes.c_int32),
+                ("width", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("box_half", ctypes.c_float)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -63,6 +70,13 @@ SIGNATURES = {
     "ddf_scene_sdf": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P, _P]),
     "ddf_shift_rays": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float, _I64, _P, _P, _P, _P]),
     "ddf_lr_cosine": (ctypes.c_float, [_I64, _I64, ctypes.c_float, ctypes.c_float]),
+    "ddf_hash_param_count": (_SZ, [ctypes.POINTER(HashDescC)]),
+    "ddf_hash_level": (ctypes.c_int, [ctypes.POINTER(HashDescC), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)]),
+    "ddf_hash_query": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _I64, _P, _P, _P]),
+    "ddf_hash_train_workspace_bytes": (_SZ, [ctypes.POINTER(HashDescC), _I64]),
+    "ddf_hash_train_step": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _P, _P, _P, _P, _I64,
+                                           ctypes.POINTER(TrainHParamsC), _P, _P, _P, _P, _SZ, _P]),
     "sdf_train_step": (ctypes.c_int, [_D, _P, _P, _P, _P, _P, _P, _I64, ctypes.POINTER(TrainHParamsC),
                                       _P, _P, _P, _P, _SZ, _P]),
 }
@@ -331,3 +345,57 @@ class DDFFunction(torch.autograd.Function):
 def ddf_apply(params, rays, desc, precision="bf16", recompute_every=0):
     """DDFFunction.apply with keyword defaults."""
     return DDFFunction.apply(params, rays, desc, precision, recompute_every)
+
+
+# ---------------------------------------------------------------- hash-grid field
+
+
+def hash_desc_c(desc) -> HashDescC:
+    return HashDescC(desc.n_levels, desc.n_feat, desc.log2_table, desc.base_res, desc.growth, desc.dir_bands,
+                     desc.width, desc.n_hidden, desc.n_out, desc.box_half)
+
+
+def hash_param_count(desc) -> int:
+    d = hash_desc_c(desc)
+    n = int(lib().ddf_hash_param_count(ctypes.byref(d)))
+    if n == 0:
+        raise DDFError(f"unsupported hash-grid description: {lib().ddf_last_error().decode()}")
+    return n
+
+
+def hash_level(desc, level):
+    """(resolution, entries, offset, hashed) of one level."""
+    d = hash_desc_c(desc)
+    res, hashed = ctypes.c_int32(), ctypes.c_int32()
+    ent, off = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().ddf_hash_level(ctypes.byref(d), int(level), ctypes.byref(res), ctypes.byref(ent), ctypes.byref(off),
+                                ctypes.byref(hashed)))
+    return res.value, ent.value, off.value, bool(hashed.value)
+
+
+def hash_query(desc, params: torch.Tensor, rays: torch.Tensor):
+    _dev(params, torch.float32, "params")
+    _dev(rays, torch.float32, "rays")
+    d = hash_desc_c(desc)
+    n = rays.shape[1]
+    t = torch.empty(n, dtype=torch.float32, device=rays.device)
+    xi = torch.empty(n, dtype=torch.float32, device=rays.device)
+    _check(lib().ddf_hash_query(ctypes.byref(d), _ptr(params), _ptr(rays), n, _ptr(t), _ptr(xi), _stream()))
+    return t, xi
+
+
+def hash_train_workspace_bytes(desc, batch) -> int:
+    d = hash_desc_c(desc)
+    return int(lib().ddf_hash_train_workspace_bytes(ctypes.byref(d), int(batch)))
+
+
+def hash_train_step(desc, params, m, v, rays, t_gt, hit, hp: TrainHParamsC, ws, loss_out=None, flag=None,
+                    grad_out=None):
+    d = hash_desc_c(desc)
+    dev = rays.device
+    loss_out = loss_out if loss_out is not None else torch.empty(4, dtype=torch.float32, device=dev)
+    flag = flag if flag is not None else torch.empty(4, dtype=torch.int32, device=dev)
+    _check(lib().ddf_hash_train_step(ctypes.byref(d), _ptr(params), _ptr(m), _ptr(v), _ptr(rays), _ptr(t_gt),
+                                     _ptr(hit), rays.shape[1], ctypes.byref(hp), _ptr(loss_out), _ptr(flag),
+                                     _ptr(grad_out), _ptr(ws), ws.numel(), _stream()))
+    return loss_out, flag

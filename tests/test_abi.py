@@ -88,3 +88,16 @@ def test_lr_cosine_matches_oracle():
         assert abs(ddf.lr_cosine(step) - O.lr_schedule(step)) <= 1e-6 * 3e-3
     assert abs(ddf.lr_cosine(30000) - 0.05 * 3e-3) <= 1e-9
     assert abs(ddf.lr_cosine(0, 100, 1.0, 0.5) - 1.0) <= 1e-7
+
+
+def test_hash_layout_matches_oracle():
+    """The library's hash-grid layout (parameter count, per-level resolution, size, offset,
+    dense or hashed) against the oracle's, for the paper's field and the test field."""
+    from oracle import hashgrid_oracle as H
+    for d in (I.HASH_PAPER, I.HASH_SMALL):
+        assert ddf.hash_param_count(d) == H.param_count(d)
+        for l, (N, e, dense, off) in enumerate(H.levels(d)):
+            assert ddf.hash_level(d, l) == (N, e, off, not dense)
+    bad = I.HashDesc(n_levels=5)
+    with pytest.raises(ddf.DDFError):
+        ddf.hash_param_count(bad)
