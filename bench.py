@@ -10,7 +10,8 @@ Further legs run in the same invocation: the other query precisions on the same
 rays; distillation training steps (65,536 rays through the 12 x 1024 net, and
 262,144 rays through the 16 x 1024 net with activations recomputed every 4
 layers, bf16 and fp32 each); and sphere tracing of a signed-distance MLP of the
-same size along the same rays (the paper's baseline).  The float64 oracle is
+same size along the same rays (the paper's baseline); and the paper's own 52 MB hash-grid
+field, queried at 1K to 2^20 rays and trained on 16,384-ray batches.  The float64 oracle is
 timed on the host cores over a bounded sample of the same rays.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16]
@@ -130,8 +131,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--legs", default="precisions,train,train_large,trace,cpu",
-                    help="comma list of extra legs: precisions, train, train_large, trace, cpu, copy")
+    ap.add_argument("--legs", default="precisions,train,train_large,trace,hash,cpu",
+                    help="comma list of extra legs: precisions, train, train_large, trace, hash, cpu, copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
@@ -225,6 +226,9 @@ def main():
     if "trace" in legs:
         out["sphere_trace"] = trace_leg(torch, ddf, I, dev, rays, timer, out, scene)
 
+    if "hash" in legs:
+        out["hash_grid"] = hash_leg(torch, ddf, I, dev, rays, timer, args.steps)
+
     if "cpu" in legs:
         out["cpu_baseline"] = cpu_oracle_baseline(desc, params_np, rays_np)
     out["wall_s_timed"] = wall
@@ -281,6 +285,61 @@ def train_leg(torch, ddf, I, dev, timer, steps, batch=65536, desc=None, recomput
                      "skipped": int(flag[0].item()), "workspace_bytes": ws.numel()}
         del ws
     res["flop_per_ray"] = fpr
+    return res
+
+
+def hash_leg(torch, ddf, I, dev, rays, timer, steps):
+    """The paper's own field, the 52 MB hash grid (16 levels x 2^19 x 2 features, 4 direction
+    bands, 2 x 64 MLP), random table N(0, 0.3): queries of the same shadow rays at 1K, 10K,
+    100K and 2^20 rays (the ray counts of the paper's latency table), and distillation steps of
+    16,384 rays (the paper's batch) against exact ray-cast targets of 1,024 ellipsoids.
+    Both query paths are timed: two-pass (lookups with level groups pinned to XCDs, then the
+    MLP) and fused (one kernel).  Algorithmic bytes per queried ray: the ray (24 B), both
+    outputs (8 B) and 16 levels x 8 corners x 2 float32 features gathered (1,024 B)."""
+    desc = I.HASH_PAPER
+    n_par = ddf.hash_param_count(desc)
+    n_entries = sum(ddf.hash_level(desc, l)[1] for l in range(desc.n_levels))
+    params = torch.from_numpy(I.hash_params(desc, n_entries, 7, table_std=0.3)).to(dev)
+    bpr = 24 + 8 + desc.n_levels * 8 * desc.n_feat * 4
+    res = {"field": "hash grid 16 x 2^19 x 2, 4 bands, 2x64 MLP", "params": n_par,
+           "bytes": 4 * n_par, "algorithmic_bytes_per_ray": bpr, "query": {}}
+    ws = torch.empty(ddf.hash_query_workspace_bytes(desc, rays.shape[1]), dtype=torch.uint8, device=dev)
+    for n in (1000, 10000, 100000, rays.shape[1]):
+        r = rays[:, :n].contiguous()
+        row = {}
+        for path in ("two_pass", "fused"):
+            kw = {"fused": True} if path == "fused" else {"ws": ws}
+            for _ in range(3):
+                ddf.hash_query(desc, params, r, **kw)
+            torch.cuda.synchronize()
+            ms = timer.time(lambda: ddf.hash_query(desc, params, r, **kw), max(10, steps))
+            row[path] = {"ms": ms, "rays_per_s": n / (ms * 1e-3), "us_per_ray": ms * 1e3 / n,
+                         "gathered_GBps": bpr * n / (ms * 1e-3) / 1e9}
+        res["query"][str(n)] = row
+    B = 16384
+    sc = I.scene_ellipsoids(1024, 3)
+    prims = torch.from_numpy(ddf.scene_prims(sc)).to(dev)
+    tr = torch.from_numpy(I.train_rays(sc, B, 1000)).to(dev)
+    t_gt, hit = ddf.cast_targets(prims, tr)
+    t_gt = torch.where(hit > 0, t_gt, torch.zeros_like(t_gt))
+    p = torch.from_numpy(I.hash_params(desc, n_entries, 36)).to(dev)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    ws = torch.empty(ddf.hash_train_workspace_bytes(desc, B), dtype=torch.uint8, device=dev)
+    loss = torch.empty(4, dtype=torch.float32, device=dev)
+    flag = torch.empty(4, dtype=torch.int32, device=dev)
+    step = [0]
+
+    def one():
+        step[0] += 1
+        hp = ddf.TrainHParamsC(3e-3, 0.9, 0.999, 1e-8, 0.3, 3.0, step[0], 0)
+        ddf.hash_train_step(desc, p, m, v, tr, t_gt, hit, hp, ws, loss_out=loss, flag=flag)
+    one()
+    torch.cuda.synchronize()
+    l0 = float(loss[0].item())
+    ms = timer.time(one, max(10, steps))
+    res["train"] = {"batch": B, "ms_per_step": ms, "train_rays_per_s": B / (ms * 1e-3), "loss_first": l0,
+                    "loss_last": float(loss[0].item()), "steps": step[0], "skipped": int(flag[0].item())}
     return res
 
 

@@ -260,9 +260,18 @@ size_t ddf_hash_param_count(const ddf_hash_desc* desc);
 int ddf_hash_level(const ddf_hash_desc* desc, int32_t level, int32_t* resolution, int64_t* entries,
                    int64_t* offset, int32_t* hashed);
 
-/* Query: params device float32 [ddf_hash_param_count]; rays [6][n]; t, xi [n]. */
+/* Bytes of the two-pass query's workspace for n rays (8 x n x 16: each ray's lookups,
+ * 2 levels per group); 0 for an unsupported desc or n < 0. */
+size_t ddf_hash_query_workspace_bytes(const ddf_hash_desc* desc, int64_t n);
+
+/* Query: params device float32 [ddf_hash_param_count]; rays [6][n]; t, xi [n]; n <= 2^31 - 1.
+ * ws == NULL: one fused kernel per ray block (lookups, direction code, MLP, heads).
+ * ws != NULL (device, >= ddf_hash_query_workspace_bytes(desc, n), else DDF_ERR_INVALID_ARG):
+ * two passes, the lookups with the table's level groups pinned to XCDs (each XCD's L2 then
+ * holds 2 of the 16 levels), then the MLP; the results are bit-identical to the fused
+ * path's.  ws is scratch, overwritten; calls sharing one ws must not overlap. */
 int ddf_hash_query(const ddf_hash_desc* desc, const float* params, const float* rays, int64_t n,
-                   float* t, float* xi, void* stream);
+                   float* t, float* xi, void* ws, size_t ws_bytes, void* stream);
 
 /* One distillation step of the hash-grid field: forward, the loss of ddf_train_step,
  * backward (the table gradient gathered with float atomics: its summation order is not

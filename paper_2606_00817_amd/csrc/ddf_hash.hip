@@ -338,6 +338,135 @@ __global__ __launch_bounds__(kHT) void hash_fwd_kernel(HashArgs a) {
   }
 }
 
+// ---- the two-pass query: the lookups with level groups pinned to XCDs, then the MLP
+// The table's levels form 8 groups of at most 2.  Workgroups are dispatched to the 8 XCDs
+// round-robin by index, so a lookup workgroup with index = g (mod 8) runs on XCD g and reads
+// group g only: each XCD's L2 holds its own group's levels instead of all of them (48 MB of
+// hashed levels against 4 MB of L2 per XCD).  The 16-level grouping pairs each of the four
+// small dense levels with one hashed level and the remaining eight hashed levels two by two.
+// Correctness does not depend on the placement, only the hit rate does.
+constexpr int kHGroups = 8;
+
+template <int NL>
+__device__ __forceinline__ int grp_level(int g, int slot) {
+  if (NL == 16) return g < 4 ? g + 4 * slot : 8 + 2 * (g - 4) + slot;
+  return (slot == 0 && g < NL) ? g : -1;
+}
+
+// G[g][r] (16 bytes): the features of group g's levels for ray r, in slot order.
+template <int NL>
+__global__ __launch_bounds__(kHT) void hash_pos_kernel(HashArgs a, float* G) {
+  __shared__ LevelTab lt;
+  stage_levels(a.L, lt);
+  __syncthreads();
+  const int g = blockIdx.x % kHGroups;
+  const int64_t r = (int64_t)(blockIdx.x / kHGroups) * blockDim.x + threadIdx.x;
+  if (r >= a.n) return;
+  float x[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) x[c] = a.rays[c * a.n + r];
+  float p[3];
+  unit_point(lt, x, p);
+  const float2* tab = reinterpret_cast<const float2*>(a.params);
+  float o[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int slot = 0; slot < 2; ++slot) {
+    const int l = grp_level<NL>(g, slot);
+    if (l < 0) continue;
+    uint32_t c[3];
+    float w[3];
+    cell((float)lt.res[l], p, c, w);
+    float f0 = 0.f, f1 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      int64_t e;
+      float wt;
+      corner(lt, l, c, w, k, e, wt);
+      const float2 t = tab[e];
+      f0 = fmaf(wt, t.x, f0);
+      f1 = fmaf(wt, t.y, f1);
+    }
+    o[2 * slot] = f0;
+    o[2 * slot + 1] = f1;
+  }
+  reinterpret_cast<f32x4*>(G)[g * a.n + r] = f32x4{o[0], o[1], o[2], o[3]};
+}
+
+// The MLP of the two-pass query: the position features from G, the direction code, the
+// layers and heads, in exactly the fused kernel's order of operations (bit-identical results).
+template <int NL, int NB, int NH>
+__global__ __launch_bounds__(kHT) void hash_mlp_kernel(HashArgs a, const float* G) {
+  __shared__ __attribute__((aligned(16))) HashSmem s;
+  stage_mlp(a.L, a.params, s);
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= a.n) return;
+  float f[2 * NL];
+#pragma unroll
+  for (int g = 0; g < kHGroups; ++g) {
+    if (grp_level<NL>(g, 0) < 0) continue;
+    const f32x4 v = reinterpret_cast<const f32x4*>(G)[g * a.n + r];
+#pragma unroll
+    for (int slot = 0; slot < 2; ++slot) {
+      const int l = grp_level<NL>(g, slot);
+      if (l < 0) continue;
+      f[2 * l] = v[2 * slot];
+      f[2 * l + 1] = v[2 * slot + 1];
+    }
+  }
+  float dv[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dv[c] = a.rays[(3 + c) * a.n + r];
+  float h[kHW], h2[kHW];
+#pragma unroll
+  for (int j = 0; j < kHW; ++j) h2[j] = s.b[0][j];
+#pragma unroll
+  for (int i = 0; i < 2 * NL; ++i) {
+    axpy_row(s.wt[0][i], f[i], h2);
+    if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+  constexpr int D0 = 2 * NL;
+#pragma unroll
+  for (int k = -1; k < NB; ++k)
+#pragma unroll
+    for (int part = 0; part < (k < 0 ? 1 : 2); ++part)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float v;
+        if (k < 0) {
+          v = dv[c];
+        } else {
+          float sn, cs;
+          sincospif(ldexpf(dv[c], k), &sn, &cs);
+          v = part == 0 ? sn : cs;
+        }
+        const int i = k < 0 ? D0 + c : D0 + 3 + 6 * k + 3 * part + c;
+        axpy_row(s.wt[0][i], v, h2);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+  for (int j = 0; j < kHW; ++j) h[j] = fmaxf(h2[j], 0.f);
+#pragma unroll
+  for (int l = 1; l < NH; ++l) {
+    hidden_relu(s.wt[l], s.b[l], h, h2);
+#pragma unroll
+    for (int j = 0; j < kHW; ++j) h[j] = h2[j];
+  }
+  float z0 = s.bh[0], z1 = s.bh[1];
+#pragma unroll
+  for (int j = 0; j < kHW; ++j) {
+    z0 = fmaf(s.wh[0][j], h[j], z0);
+    z1 = fmaf(s.wh[1][j], h[j], z1);
+  }
+  if (a.mode == 0) {
+    a.out0[r] = softplusf_(z0);
+    a.out1[r] = sigmoidf_(z1);
+  } else {
+    a.out0[r] = z0;
+    a.out1[r] = z1;
+  }
+}
+
 __device__ inline void store_row(float* dst, const float (&v)[kHW]) {
   f32x4* d4 = reinterpret_cast<f32x4*>(dst);
 #pragma unroll
@@ -579,15 +708,25 @@ HashWs hash_ws(const HashLayout& L, int64_t batch) {
 // Encodings with a compiled kernel: (levels, direction bands).
 bool hash_shape_supported(int nl, int nb, int nh) { return (nl == 16 || nl == 6) && nb == 4 && nh == 2; }
 
+// G == nullptr: the fused one-kernel query; else the two-pass query through G
+// (kHGroups x n x 16 bytes).
 int run_hash_forward(const HashLayout& L, const float* params, const float* rays, int64_t n, int mode, float* o0,
-                     float* o1, hipStream_t st) {
+                     float* o1, float* G, hipStream_t st) {
   HashArgs a{};
   a.L = L; a.params = params; a.rays = rays; a.n = n; a.mode = mode; a.out0 = o0; a.out1 = o1;
   const unsigned blocks = (unsigned)((n + kHT - 1) / kHT);
-  if (L.n_levels == 16)
-    hash_fwd_kernel<16, 4, 2><<<blocks, kHT, 0, st>>>(a);
-  else
-    hash_fwd_kernel<6, 4, 2><<<blocks, kHT, 0, st>>>(a);
+  if (G == nullptr) {
+    if (L.n_levels == 16)
+      hash_fwd_kernel<16, 4, 2><<<blocks, kHT, 0, st>>>(a);
+    else
+      hash_fwd_kernel<6, 4, 2><<<blocks, kHT, 0, st>>>(a);
+  } else if (L.n_levels == 16) {
+    hash_pos_kernel<16><<<blocks * kHGroups, kHT, 0, st>>>(a, G);
+    hash_mlp_kernel<16, 4, 2><<<blocks, kHT, 0, st>>>(a, G);
+  } else {
+    hash_pos_kernel<6><<<blocks * kHGroups, kHT, 0, st>>>(a, G);
+    hash_mlp_kernel<6, 4, 2><<<blocks, kHT, 0, st>>>(a, G);
+  }
   return hip_status(hipGetLastError(), "hash forward launch");
 }
 
@@ -638,8 +777,13 @@ int ddf_hash_level(const ddf_hash_desc* d, int32_t level, int32_t* resolution, i
   return DDF_OK;
 }
 
+size_t ddf_hash_query_workspace_bytes(const ddf_hash_desc* d, int64_t n) {
+  if (check_hash_desc(d) != DDF_OK || n < 0) return 0;
+  return (size_t)n * kHGroups * 16;
+}
+
 int ddf_hash_query(const ddf_hash_desc* d, const float* params, const float* rays, int64_t n, float* t, float* xi,
-                   void* stream) {
+                   void* ws, size_t ws_bytes, void* stream) {
   int rc;
   if ((rc = check_hash_desc(d))) return rc;
   if (n < 0 || n > (int64_t)INT32_MAX) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
@@ -647,8 +791,14 @@ int ddf_hash_query(const ddf_hash_desc* d, const float* params, const float* ray
   if ((rc = check_ptr(params, "params")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(t, "t")) ||
       (rc = check_ptr(xi, "xi")))
     return rc;
+  if (ws != nullptr) {
+    if ((rc = check_ptr(ws, "ws"))) return rc;
+    if (ws_bytes < (size_t)n * kHGroups * 16)
+      return fail(DDF_ERR_INVALID_ARG, "workspace %zu bytes < %zu", ws_bytes, (size_t)n * kHGroups * 16);
+  }
   g_err_clear();
-  return run_hash_forward(make_hash_layout(*d), params, rays, n, 0, t, xi, (hipStream_t)stream);
+  return run_hash_forward(make_hash_layout(*d), params, rays, n, 0, t, xi, static_cast<float*>(ws),
+                          (hipStream_t)stream);
 }
 
 size_t ddf_hash_train_workspace_bytes(const ddf_hash_desc* d, int64_t batch) {

@@ -73,7 +73,8 @@ SIGNATURES = {
     "ddf_hash_param_count": (_SZ, [ctypes.POINTER(HashDescC)]),
     "ddf_hash_level": (ctypes.c_int, [ctypes.POINTER(HashDescC), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                       ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)]),
-    "ddf_hash_query": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _I64, _P, _P, _P]),
+    "ddf_hash_query_workspace_bytes": (_SZ, [ctypes.POINTER(HashDescC), _I64]),
+    "ddf_hash_query": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _I64, _P, _P, _P, _SZ, _P]),
     "ddf_hash_train_workspace_bytes": (_SZ, [ctypes.POINTER(HashDescC), _I64]),
     "ddf_hash_train_step": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _P, _P, _P, _P, _I64,
                                            ctypes.POINTER(TrainHParamsC), _P, _P, _P, _P, _SZ, _P]),
@@ -373,14 +374,24 @@ def hash_level(desc, level):
     return res.value, ent.value, off.value, bool(hashed.value)
 
 
-def hash_query(desc, params: torch.Tensor, rays: torch.Tensor):
+def hash_query_workspace_bytes(desc, n) -> int:
+    d = hash_desc_c(desc)
+    return int(lib().ddf_hash_query_workspace_bytes(ctypes.byref(d), int(n)))
+
+
+def hash_query(desc, params: torch.Tensor, rays: torch.Tensor, ws: torch.Tensor | None = None, fused: bool = False):
+    """(t, xi) of rays [6][n].  fused=True: the one-kernel path; else the two-pass path through
+    `ws` (allocated here when not given)."""
     _dev(params, torch.float32, "params")
     _dev(rays, torch.float32, "rays")
     d = hash_desc_c(desc)
     n = rays.shape[1]
     t = torch.empty(n, dtype=torch.float32, device=rays.device)
     xi = torch.empty(n, dtype=torch.float32, device=rays.device)
-    _check(lib().ddf_hash_query(ctypes.byref(d), _ptr(params), _ptr(rays), n, _ptr(t), _ptr(xi), _stream()))
+    if not fused and ws is None and n > 0:
+        ws = torch.empty(hash_query_workspace_bytes(desc, n), dtype=torch.uint8, device=rays.device)
+    wp, wb = (None, 0) if fused or ws is None else (_ptr(ws), ws.numel() * ws.element_size())
+    _check(lib().ddf_hash_query(ctypes.byref(d), _ptr(params), _ptr(rays), n, _ptr(t), _ptr(xi), wp, wb, _stream()))
     return t, xi
 
 

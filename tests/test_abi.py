@@ -98,6 +98,9 @@ def test_hash_layout_matches_oracle():
         assert ddf.hash_param_count(d) == H.param_count(d)
         for l, (N, e, dense, off) in enumerate(H.levels(d)):
             assert ddf.hash_level(d, l) == (N, e, off, not dense)
+        # the two-pass query keeps 8 groups x 16 bytes of lookups per ray
+        assert ddf.hash_query_workspace_bytes(d, 1000) == 1000 * 128
     bad = I.HashDesc(n_levels=5)
     with pytest.raises(ddf.DDFError):
         ddf.hash_param_count(bad)
+    assert ddf.hash_query_workspace_bytes(bad, 1000) == 0

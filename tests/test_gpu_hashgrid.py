@@ -37,21 +37,22 @@ def _edge_rays(desc, n, seed):
     return np.ascontiguousarray(np.concatenate([o, d], axis=1).T.astype(np.float32))
 
 
+@pytest.mark.parametrize("fused", [False, True], ids=["two-pass", "fused"])
 @pytest.mark.parametrize("desc", [I.HASH_SMALL, I.HASH_PAPER], ids=["6-level", "paper-16-level"])
 @pytest.mark.parametrize("n", [1000, 33, 1])
-def test_hash_query_matches_oracle(desc, n):
+def test_hash_query_matches_oracle(desc, n, fused):
     dev = cuda()
     params = _params(desc, 31)
     sc = I.scene_mixed(256, 2)
     rays = I.free_rays(sc, n, 32) if n > 1 else I.free_rays(sc, 8, 32)[:, :1]
     if n >= 64:
         rays = np.concatenate([rays[:, : n - 64], _edge_rays(desc, 64, 33)], axis=1)
-    t, xi = ddf.hash_query(desc, _t(params, dev), _t(rays, dev))
+    t, xi = ddf.hash_query(desc, _t(params, dev), _t(rays, dev), fused=fused)
     torch.cuda.synchronize()
     t64, x64, zt, zx = H.hash_query(desc, params, rays, coords="fp32")
     dt = np.abs(t.cpu().numpy() - t64)
     dx = np.abs(xi.cpu().numpy() - x64)
-    print(f"hash query {desc.n_levels} levels n={n}: max |dt| {dt.max():.2e}, max |dxi| {dx.max():.2e}")
+    print(f"hash query {desc.n_levels} levels n={n} fused={fused}: max |dt| {dt.max():.2e}, max |dxi| {dx.max():.2e}")
     # the oracle takes the cells from float32 grid coordinates as the kernel does; what is
     # left is float32 rounding in the lookups (8 weighted terms per level) and in the
     # 59 + 64 + 64-term MLP: a few hundred roundings of values of order one
@@ -59,13 +60,21 @@ def test_hash_query_matches_oracle(desc, n):
 
 
 def test_hash_query_2p20_paper_field():
+    """The benchmark's query (2^20 shadow rays, two-pass) on sampled rays; the fused path
+    gives the same bits; a workspace one byte short is refused before any launch."""
     dev = cuda()
     desc = I.HASH_PAPER
     params = _params(desc, 34)
     sc = I.scene_mixed(256, 2)
     rays = I.shadow_rays(sc, 1 << 20, 12)
-    t, xi = ddf.hash_query(desc, _t(params, dev), _t(rays, dev))
+    pd, rd = _t(params, dev), _t(rays, dev)
+    t, xi = ddf.hash_query(desc, pd, rd)
+    tf, xf = ddf.hash_query(desc, pd, rd, fused=True)
     torch.cuda.synchronize()
+    assert torch.equal(t, tf) and torch.equal(xi, xf)
+    short = torch.empty(ddf.hash_query_workspace_bytes(desc, rays.shape[1]) - 1, dtype=torch.uint8, device=dev)
+    with pytest.raises(ddf.DDFError, match="workspace"):
+        ddf.hash_query(desc, pd, rd, ws=short)
     t, xi = t.cpu().numpy(), xi.cpu().numpy()
     assert np.isfinite(t).all() and (t >= 0).all() and (xi >= 0).all() and (xi <= 1).all()
     idx = np.linspace(0, rays.shape[1] - 1, 512).astype(np.int64)
