@@ -268,8 +268,9 @@ size_t ddf_hash_query_workspace_bytes(const ddf_hash_desc* desc, int64_t n);
  * ws == NULL: one fused kernel per ray block (lookups, direction code, MLP, heads).
  * ws != NULL (device, >= ddf_hash_query_workspace_bytes(desc, n), else DDF_ERR_INVALID_ARG):
  * two passes, the lookups with the table's level groups pinned to XCDs (each XCD's L2 then
- * holds 2 of the 16 levels), then the MLP; the results are bit-identical to the fused
- * path's.  ws is scratch, overwritten; calls sharing one ws must not overlap. */
+ * holds 2 of the 16 levels), then the MLP on the matrix cores (fp32); the lookups are
+ * bit-identical to the fused path's, the MLP sums in another order (float32 rounding).
+ * ws is scratch, overwritten; calls sharing one ws must not overlap. */
 int ddf_hash_query(const ddf_hash_desc* desc, const float* params, const float* rays, int64_t n,
                    float* t, float* xi, void* ws, size_t ws_bytes, void* stream);
 

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 
+#include "ddf_chain.h"
 #include "ddf_internal.h"
 #include "ddf_train.h"
 
@@ -376,15 +377,42 @@ __global__ __launch_bounds__(kHT) void hash_pos_kernel(HashArgs a, float* G) {
     uint32_t c[3];
     float w[3];
     cell((float)lt.res[l], p, c, w);
+    const uint32_t n1 = (uint32_t)lt.res[l] + 1u;
+    const float* base = a.params + 2 * lt.off[l];
+    const bool dense = lt.dense[l];
     float f0 = 0.f, f1 = 0.f;
+    // the 8 corners as 4 pairs along x, (v0, v1, v2) and (v0 + 1, v1, v2): densely indexed,
+    // the pair is 16 contiguous bytes; hashed, x enters the hash with multiplier 1, so for an
+    // even v0 the pair is the aligned 16 bytes {i & ~1, i | 1} and only an odd v0 needs a
+    // second load.  Products and sums in the same order as corner-by-corner.
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      int64_t e;
-      float wt;
-      corner(lt, l, c, w, k, e, wt);
-      const float2 t = tab[e];
-      f0 = fmaf(wt, t.x, f0);
-      f1 = fmaf(wt, t.y, f1);
+    for (int m = 0; m < 4; ++m) {
+      const uint32_t v0 = c[0], v1 = c[1] + (m & 1), v2 = c[2] + (m >> 1);
+      const float wy = (m & 1) ? w[1] : 1.f - w[1], wz = (m >> 1) ? w[2] : 1.f - w[2];
+      const float wa = ((1.f - w[0]) * wy) * wz, wb = (w[0] * wy) * wz;
+      float2 ca, cb;
+      if (dense) {
+        const uint32_t i0 = v0 + n1 * (v1 + n1 * v2);
+        const f32x4 q = *reinterpret_cast<const f32x4*>(base + 2 * (size_t)i0);
+        ca = float2{q[0], q[1]};
+        cb = float2{q[2], q[3]};
+      } else {
+        const uint32_t h = (v1 * kPrime1) ^ (v2 * kPrime2);
+        const uint32_t i0 = (v0 ^ h) & lt.tmask;
+        const f32x4 q = *reinterpret_cast<const f32x4*>(base + 2 * (size_t)(i0 & ~1u));
+        const bool odd = i0 & 1u;
+        ca = odd ? float2{q[2], q[3]} : float2{q[0], q[1]};
+        if (v0 & 1u) {
+          const uint32_t i1 = ((v0 + 1u) ^ h) & lt.tmask;
+          cb = *reinterpret_cast<const float2*>(base + 2 * (size_t)i1);
+        } else {
+          cb = odd ? float2{q[0], q[1]} : float2{q[2], q[3]};
+        }
+      }
+      f0 = fmaf(wa, ca.x, f0);
+      f1 = fmaf(wa, ca.y, f1);
+      f0 = fmaf(wb, cb.x, f0);
+      f1 = fmaf(wb, cb.y, f1);
     }
     o[2 * slot] = f0;
     o[2 * slot + 1] = f1;
@@ -392,78 +420,153 @@ __global__ __launch_bounds__(kHT) void hash_pos_kernel(HashArgs a, float* G) {
   reinterpret_cast<f32x4*>(G)[g * a.n + r] = f32x4{o[0], o[1], o[2], o[3]};
 }
 
-// The MLP of the two-pass query: the position features from G, the direction code, the
-// layers and heads, in exactly the fused kernel's order of operations (bit-identical results).
-template <int NL, int NB, int NH>
-__global__ __launch_bounds__(kHT) void hash_mlp_kernel(HashArgs a, const float* G) {
-  __shared__ __attribute__((aligned(16))) HashSmem s;
-  stage_mlp(a.L, a.params, s);
-  __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= a.n) return;
-  float f[2 * NL];
+// The MLP of the two-pass query on the matrix cores (fp32 32x32x2 MFMA), with the rays as the
+// product's columns: C[neuron][ray] = sum_k W[neuron][k] X[ray][k].  At step s lane l supplies
+// W[n0 + l % 32][k(s, l / 32)] and X[ray0 + l % 32][k(s, l / 32)] and holds neurons
+// n0 + acc_row(v, l) of ray ray0 + l % 32.  After bias and ReLU these are exactly the values
+// lane l supplies at step s = 16 ct + v of the next layer when that layer takes its inputs in
+// the order k(s, p) = 32 (s / 16) + 8 ((s % 16) / 4) + 4 p + s % 4 (the weights are staged in
+// that order), so the hidden activations never leave the registers.  The first layer takes
+// its inputs in the natural order k(s, p) = 2 s + p.
+struct HashFrag {
+  f32x4 w1[2][8][64];     // [neuron tile][step / 4][lane] -> steps 4j .. 4j + 3
+  f32x4 w2[2][8][64];
+  float b1[kHW], b2[kHW];
+  float wh[2][kHW];
+  float bh[2];
+};
+
+__device__ __forceinline__ int hid_k(int s, int p) { return 32 * (s >> 4) + 8 * ((s & 15) >> 2) + 4 * p + (s & 3); }
+
+__device__ __forceinline__ void stage_frag(const HashLayout& L, const float* __restrict__ params, HashFrag& f) {
+  const float* W1 = params + L.w_off[0];
+  const float* W2 = params + L.w_off[1];
+  float* w1 = reinterpret_cast<float*>(f.w1);
+  float* w2 = reinterpret_cast<float*>(f.w2);
+  for (int e = threadIdx.x; e < 2 * 32 * 64; e += blockDim.x) {
+    const int ct = e >> 11, st = (e >> 6) & 31, ln = e & 63;
+    const int n = ct * 32 + (ln & 31), p = ln >> 5;
+    const int k1 = 2 * st + p;
+    const int dst = ((ct * 8 + (st >> 2)) * 64 + ln) * 4 + (st & 3);
+    w1[dst] = k1 < L.d_in ? W1[n * L.d_in + k1] : 0.f;
+    w2[dst] = W2[n * kHW + hid_k(st, p)];
+  }
+  for (int j = threadIdx.x; j < kHW; j += blockDim.x) {
+    f.b1[j] = params[L.b_off[0] + j];
+    f.b2[j] = params[L.b_off[1] + j];
+    f.wh[0][j] = params[L.wh_off + j];
+    f.wh[1][j] = params[L.wh_off + kHW + j];
+  }
+  if (threadIdx.x < 2) f.bh[threadIdx.x] = params[L.bh_off + threadIdx.x];
+}
+
+// One layer: acc[rt][ct] = b + W X^T over the 32 steps (wf: the layer's staged fragments).
+__device__ __forceinline__ void frag_layer(const f32x4 (&wf)[2][8][64], const float* b, const float (&x)[2][32],
+                                           int lane, f32x16 (&acc)[2][2]) {
 #pragma unroll
-  for (int g = 0; g < kHGroups; ++g) {
-    if (grp_level<NL>(g, 0) < 0) continue;
-    const f32x4 v = reinterpret_cast<const f32x4*>(G)[g * a.n + r];
+  for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
-    for (int slot = 0; slot < 2; ++slot) {
-      const int l = grp_level<NL>(g, slot);
-      if (l < 0) continue;
-      f[2 * l] = v[2 * slot];
-      f[2 * l + 1] = v[2 * slot + 1];
+    for (int v = 0; v < 16; ++v) {
+      const float bv = b[ct * 32 + acc_row(v, lane)];
+      acc[0][ct][v] = bv;
+      acc[1][ct][v] = bv;
     }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const f32x4 wa = wf[0][j][lane], wb = wf[1][j][lane];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        acc[rt][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(wa[q], x[rt][4 * j + q], acc[rt][0], 0, 0, 0);
+        acc[rt][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(wb[q], x[rt][4 * j + q], acc[rt][1], 0, 0, 0);
+      }
   }
-  float dv[3];
+}
+
+// Each wave takes 64 rays (two 32-ray column tiles); lane l works on rays l % 32 of both tiles
+// and, of each layer's inputs, on the half with parity l / 32.
+template <int NL, int NB>
+__global__ __launch_bounds__(kHT) void hash_mlp_kernel(HashArgs a, const float* G) {
+  __shared__ __attribute__((aligned(16))) HashFrag f;
+  stage_frag(a.L, a.params, f);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, p = lane >> 5;
+  const int64_t ray0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+  if (ray0 >= a.n) return;   // whole waves only
+  constexpr int ND = 3 * (1 + 2 * NB);
+  float x[2][32];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) dv[c] = a.rays[(3 + c) * a.n + r];
-  float h[kHW], h2[kHW];
+  for (int rt = 0; rt < 2; ++rt) {
+    // rays past n repeat the last ray and are not stored
+    const int64_t r = min(ray0 + rt * 32 + (lane & 31), a.n - 1);
 #pragma unroll
-  for (int j = 0; j < kHW; ++j) h2[j] = s.b[0][j];
+    for (int g = 0; g < kHGroups; ++g) {
+      if (grp_level<NL>(g, 0) < 0) continue;
+      const f32x4 v = reinterpret_cast<const f32x4*>(G)[g * a.n + r];
 #pragma unroll
-  for (int i = 0; i < 2 * NL; ++i) {
-    axpy_row(s.wt[0][i], f[i], h2);
-    if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
-  }
-  constexpr int D0 = 2 * NL;
+      for (int slot = 0; slot < 2; ++slot) {
+        const int l = grp_level<NL>(g, slot);
+        if (l < 0) continue;
+        x[rt][l] = p ? v[2 * slot + 1] : v[2 * slot];
+      }
+    }
+    float dv[3];
 #pragma unroll
-  for (int k = -1; k < NB; ++k)
+    for (int c = 0; c < 3; ++c) dv[c] = a.rays[(3 + c) * a.n + r];
+    float df[ND + 1];
 #pragma unroll
-    for (int part = 0; part < (k < 0 ? 1 : 2); ++part)
+    for (int c = 0; c < 3; ++c) df[c] = dv[c];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        float v;
-        if (k < 0) {
-          v = dv[c];
-        } else {
-          float sn, cs;
-          sincospif(ldexpf(dv[c], k), &sn, &cs);
-          v = part == 0 ? sn : cs;
-        }
-        const int i = k < 0 ? D0 + c : D0 + 3 + 6 * k + 3 * part + c;
-        axpy_row(s.wt[0][i], v, h2);
-        __builtin_amdgcn_sched_barrier(0);
+        float sn, cs;
+        sincospif(ldexpf(dv[c], k), &sn, &cs);
+        df[3 + 6 * k + c] = sn;
+        df[6 + 6 * k + c] = cs;
       }
+    df[ND] = 0.f;
 #pragma unroll
-  for (int j = 0; j < kHW; ++j) h[j] = fmaxf(h2[j], 0.f);
-#pragma unroll
-  for (int l = 1; l < NH; ++l) {
-    hidden_relu(s.wt[l], s.b[l], h, h2);
-#pragma unroll
-    for (int j = 0; j < kHW; ++j) h[j] = h2[j];
+    for (int st = NL; st < 32; ++st) {
+      const int i0 = 2 * (st - NL);
+      const float v0 = i0 < ND ? df[i0] : 0.f, v1 = i0 + 1 < ND ? df[i0 + 1] : 0.f;
+      x[rt][st] = p ? v1 : v0;
+    }
   }
-  float z0 = s.bh[0], z1 = s.bh[1];
+  f32x16 acc[2][2];
+  frag_layer(f.w1, f.b1, x, lane, acc);
 #pragma unroll
-  for (int j = 0; j < kHW; ++j) {
-    z0 = fmaf(s.wh[0][j], h[j], z0);
-    z1 = fmaf(s.wh[1][j], h[j], z1);
-  }
-  if (a.mode == 0) {
-    a.out0[r] = softplusf_(z0);
-    a.out1[r] = sigmoidf_(z1);
-  } else {
-    a.out0[r] = z0;
-    a.out1[r] = z1;
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) x[rt][16 * ct + v] = fmaxf(acc[rt][ct][v], 0.f);
+  frag_layer(f.w2, f.b2, x, lane, acc);
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    float z0 = 0.f, z1 = 0.f;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int n = ct * 32 + acc_row(v, lane);
+        const float hv = fmaxf(acc[rt][ct][v], 0.f);
+        z0 = fmaf(f.wh[0][n], hv, z0);
+        z1 = fmaf(f.wh[1][n], hv, z1);
+      }
+    z0 = z0 + __shfl_xor(z0, 32) + f.bh[0];
+    z1 = z1 + __shfl_xor(z1, 32) + f.bh[1];
+    const int64_t r = ray0 + rt * 32 + (lane & 31);
+    if (p == rt && r < a.n) {
+      if (a.mode == 0) {
+        a.out0[r] = softplusf_(z0);
+        a.out1[r] = sigmoidf_(z1);
+      } else {
+        a.out0[r] = z0;
+        a.out1[r] = z1;
+      }
+    }
   }
 }
 
@@ -722,10 +825,10 @@ int run_hash_forward(const HashLayout& L, const float* params, const float* rays
       hash_fwd_kernel<6, 4, 2><<<blocks, kHT, 0, st>>>(a);
   } else if (L.n_levels == 16) {
     hash_pos_kernel<16><<<blocks * kHGroups, kHT, 0, st>>>(a, G);
-    hash_mlp_kernel<16, 4, 2><<<blocks, kHT, 0, st>>>(a, G);
+    hash_mlp_kernel<16, 4><<<blocks, kHT, 0, st>>>(a, G);
   } else {
     hash_pos_kernel<6><<<blocks * kHGroups, kHT, 0, st>>>(a, G);
-    hash_mlp_kernel<6, 4, 2><<<blocks, kHT, 0, st>>>(a, G);
+    hash_mlp_kernel<6, 4><<<blocks, kHT, 0, st>>>(a, G);
   }
   return hip_status(hipGetLastError(), "hash forward launch");
 }
