@@ -416,3 +416,35 @@ def planted_box_sdf(desc, half, seed, bias=1.0, noise=0.05):
         Wh[0, 0] = 1.0
     bh[0] = -B
     return p.astype(np.float32)
+
+
+# ---- the shading workload: a ground slab with objects above it, a camera and a light
+
+@dataclasses.dataclass(frozen=True)
+class View:
+    """Pinhole camera: eye, look-at target, up hint, vertical field of view (radians), size."""
+    eye: tuple = (0.0, 1.6, 3.2)
+    target: tuple = (0.0, -0.5, 0.0)
+    up: tuple = (0.0, 1.0, 0.0)
+    fov_y: float = math.radians(45.0)
+    width: int = 512
+    height: int = 512
+
+
+SHADE_LIGHT = (1.2, 2.8, 0.8)   # point light of the shading workload (outside the box)
+AO_RAYS = 16                    # AO rays per pixel of the shading workload
+
+
+def scene_ground(n: int, seed: int) -> Scene:
+    """A flat ground slab (top face at y = -1) under n spheres and ellipsoids (sizes as in
+    scene_mixed) whose centres lie in [-1, 1] x [-0.8, 0.9] x [-1, 1]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = np.concatenate([[[0.0, -1.02, 0.0]],
+                        np.stack([rng.uniform(-1, 1, n), rng.uniform(-0.8, 0.9, n), rng.uniform(-1, 1, n)], 1)])
+    is_sphere = rng.uniform(size=n) < 0.5
+    r = rng.uniform(0.08, 0.3, n)
+    a = rng.uniform(0.05, 0.25, (n, 3))
+    axes = np.concatenate([[[1.45, 0.02, 1.45]], np.where(is_sphere[:, None], r[:, None], a)])
+    rots = _random_rotations(rng, n)
+    rots[is_sphere] = np.eye(3)
+    return Scene(c, axes, np.concatenate([np.eye(3)[None], rots]))
