@@ -285,6 +285,46 @@ int ddf_hash_train_step(const ddf_hash_desc* desc, float* params, float* adam_m,
                         const ddf_train_hparams* hp, float* loss_out, int32_t* nonfinite_flag,
                         float* grad_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------ shading consumers */
+
+/* A renderer's use of the field (Sec. III-C; shadows and ambient occlusion against a
+ * reference ray tracer, Sec. IV-F, Table VI).  Primary visibility comes from the exact scene;
+ * the secondary rays go to the field (ddf_query / ddf_hash_query) or, for the reference maps,
+ * to ddf_cast_targets; ddf_shade turns the answers into per-pixel maps.
+ *
+ * Pinhole camera: pixel (i, j), row 0 at the top, looks along
+ * normalise(f + s_x r + s_y u), s_x = (2 (i + 0.5) / W - 1) tan(fov_y / 2) W / H,
+ * s_y = (1 - 2 (j + 0.5) / H) tan(fov_y / 2), f = normalise(target - eye),
+ * r = normalise(f x up), u = r x f (frame computed on the host in double). */
+typedef struct {
+  float eye[3], target[3], up[3];
+  float fov_y;                /* radians, in (0, 3.1) */
+  int32_t width, height;      /* width * height <= 2^31 - 1 */
+} ddf_camera;
+
+/* G-buffer of the W x H pixels (P = W H, row-major): gbuf [6][P] float32 = hit point and
+ * outward unit normal (zeros for background), hit [P] uint8.  prims [n_prims][16] as for
+ * ddf_cast_targets (device); all device pointers 16-byte aligned. */
+int ddf_primary_gbuffer(const ddf_camera* cam, const float* prims, int32_t n_prims, float* gbuf, uint8_t* hit,
+                        void* stream);
+
+/* Secondary rays [6][n_px (1 + n_ao)], pixel-major: for pixel i, ray i (1 + n_ao) goes from
+ * o = p + offset n toward light (host, 3 floats), rays i (1 + n_ao) + 1 + k are cosine-weighted
+ * over the hemisphere around n (Malley's method in the orthonormal basis of Duff et al.
+ * 2017) from uniforms u [2][n_px n_ao] (device; u[0] the radius draw, u[1] the angle draw).
+ * Background pixels get finite dummy rays (p, +z).  0 <= n_ao <= 1024, offset >= 0,
+ * n_px (1 + n_ao) <= 2^31 - 1. */
+int ddf_secondary_rays(const float* gbuf, const uint8_t* hit, int64_t n_px, const float* light, int32_t n_ao,
+                       const float* u, float offset, float* rays, void* stream);
+
+/* Per-pixel maps from the answers t [n_px (1 + n_ao)] and exactly one of xi (the field's,
+ * a ray hits when xi > 0.5) or ray_hit (uint8, the exact cast's): shadow[i] = 1 when the
+ * shadow ray hits with t < |light - o|, ao[i] = the share of AO rays that hit with
+ * t < ao_radius (> 0; +inf counts every hit).  Background pixels get 0 and 0. */
+int ddf_shade(const float* t, const float* xi, const uint8_t* ray_hit, const float* gbuf, const uint8_t* hit,
+              int64_t n_px, const float* light, int32_t n_ao, float offset, float ao_radius, float* shadow, float* ao,
+              void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -42,6 +42,11 @@ class HashDescC(ctypes.Structure):
                 ("box_half", ctypes.c_float)]
 
 
+class CameraC(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("target", ctypes.c_float * 3), ("up", ctypes.c_float * 3),
+                ("fov_y", ctypes.c_float), ("width", ctypes.c_int32), ("height", ctypes.c_int32)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -78,6 +83,11 @@ SIGNATURES = {
     "ddf_hash_train_workspace_bytes": (_SZ, [ctypes.POINTER(HashDescC), _I64]),
     "ddf_hash_train_step": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _P, _P, _P, _P, _I64,
                                            ctypes.POINTER(TrainHParamsC), _P, _P, _P, _P, _SZ, _P]),
+    "ddf_primary_gbuffer": (ctypes.c_int, [ctypes.POINTER(CameraC), _P, ctypes.c_int32, _P, _P, _P]),
+    "ddf_secondary_rays": (ctypes.c_int, [_P, _P, _I64, ctypes.POINTER(ctypes.c_float), ctypes.c_int32, _P,
+                                          ctypes.c_float, _P, _P]),
+    "ddf_shade": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
+                                 ctypes.c_float, ctypes.c_float, _P, _P, _P]),
     "sdf_train_step": (ctypes.c_int, [_D, _P, _P, _P, _P, _P, _P, _I64, ctypes.POINTER(TrainHParamsC),
                                       _P, _P, _P, _P, _SZ, _P]),
 }
@@ -410,3 +420,51 @@ def hash_train_step(desc, params, m, v, rays, t_gt, hit, hp: TrainHParamsC, ws, 
                                      _ptr(hit), rays.shape[1], ctypes.byref(hp), _ptr(loss_out), _ptr(flag),
                                      _ptr(grad_out), _ptr(ws), ws.numel(), _stream()))
     return loss_out, flag
+
+
+# ---- shading consumers
+
+def camera_c(view) -> CameraC:
+    """ctypes camera from any object with eye, target, up, fov_y, width, height."""
+    f3 = ctypes.c_float * 3
+    return CameraC(f3(*view.eye), f3(*view.target), f3(*view.up), view.fov_y, view.width, view.height)
+
+
+def primary_gbuffer(view, prims: torch.Tensor):
+    """(gbuf [6][P] float32: hit point and outward normal, hit [P] uint8) of the view's pixels."""
+    _dev(prims, torch.float32, "prims")
+    P = view.width * view.height
+    gbuf = torch.empty((6, P), dtype=torch.float32, device=prims.device)
+    hit = torch.empty(P, dtype=torch.uint8, device=prims.device)
+    cam = camera_c(view)
+    _check(lib().ddf_primary_gbuffer(ctypes.byref(cam), _ptr(prims), prims.shape[0], _ptr(gbuf), _ptr(hit),
+                                     _stream()))
+    return gbuf, hit
+
+
+def secondary_rays(gbuf: torch.Tensor, hit: torch.Tensor, light, n_ao: int, u: torch.Tensor | None,
+                   offset: float, out: torch.Tensor | None = None):
+    """Rays [6][P (1 + n_ao)]: per pixel the shadow ray, then n_ao AO rays (u [2][P n_ao])."""
+    _dev(gbuf, torch.float32, "gbuf")
+    _dev(hit, torch.uint8, "hit")
+    P = hit.shape[0]
+    if n_ao > 0:
+        _dev(u, torch.float32, "u")
+    rays = out if out is not None else torch.empty((6, P * (1 + n_ao)), dtype=torch.float32, device=gbuf.device)
+    L = (ctypes.c_float * 3)(*light)
+    _check(lib().ddf_secondary_rays(_ptr(gbuf), _ptr(hit), P, L, int(n_ao), _ptr(u) if n_ao > 0 else None,
+                                    float(offset), _ptr(rays), _stream()))
+    return rays
+
+
+def shade(t: torch.Tensor, gbuf: torch.Tensor, hit: torch.Tensor, light, n_ao: int, offset: float,
+          xi: torch.Tensor | None = None, ray_hit: torch.Tensor | None = None, ao_radius: float = float("inf")):
+    """(shadow [P], ao [P]) from the answers t and xi (the field) or ray_hit (the exact cast)."""
+    _dev(t, torch.float32, "t")
+    P = hit.shape[0]
+    shadow = torch.empty(P, dtype=torch.float32, device=t.device)
+    ao = torch.empty(P, dtype=torch.float32, device=t.device)
+    L = (ctypes.c_float * 3)(*light)
+    _check(lib().ddf_shade(_ptr(t), _ptr(xi), _ptr(ray_hit), _ptr(gbuf), _ptr(hit), P, L, int(n_ao), float(offset),
+                           float(ao_radius), _ptr(shadow), _ptr(ao), _stream()))
+    return shadow, ao
