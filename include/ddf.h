@@ -325,6 +325,23 @@ int ddf_shade(const float* t, const float* xi, const uint8_t* ray_hit, const flo
               int64_t n_px, const float* light, int32_t n_ao, float offset, float ao_radius, float* shadow, float* ao,
               void* stream);
 
+/* ------------------------------------------------------------------ training rays */
+
+/* Training rays [6][n] on the GPU (Sec. III-B: rays from the surface in every direction,
+ * for the secondary visibility shadows and AO need, and rays of the rendered views, here
+ * free rays from the box).  mode 0: surface rays, 1: free rays, 2: surface at even and free
+ * at odd positions.  A surface ray starts at c + R (a s) + offset n on a primitive chosen
+ * with probability proportional to its surface area (Thomsen's ellipsoid approximation),
+ * s uniform on the sphere, n the outward normal; a free ray starts uniform in
+ * [-box_half, box_half]^3; a start strictly inside another (any, for free rays) primitive is
+ * rejected and the next candidate taken, up to `tries` (1..16; the last is kept).
+ * Directions are uniform on the sphere.  u [3 tries + 2][n] device uniforms in [0, 1): rows
+ * 3j .. 3j + 2 drive candidate j (primitive choice and sphere point, or x, y, z), the last
+ * two the direction (z = 1 - 2 u, phi = 2 pi u').  cdf_ws: device scratch of n_prims floats
+ * (overwritten with the cumulative area weights).  n <= 2^26. */
+int ddf_sample_rays(const float* prims, int32_t n_prims, const float* u, int64_t n, int32_t mode, float box_half,
+                    float offset, int32_t tries, float* cdf_ws, float* rays, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -173,6 +173,103 @@ __global__ __launch_bounds__(kShadeThreads) void shade_kernel(const float* __res
   ao[i] = a;
 }
 
+// ---- training rays: area-weighted surface rays and free rays, with rejection
+
+// Cumulative surface-area weights of the primitives (Knud Thomsen's ellipsoid area
+// approximation, exact for spheres), normalised to end at 1; one thread, in double.
+__global__ void area_cdf_kernel(const float* __restrict__ prims, int n_prims, float* __restrict__ cdf) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  constexpr double kP = 1.6075;
+  double total = 0.0;
+  for (int k = 0; k < n_prims; ++k) {
+    const float* q = prims + (int64_t)k * kPrimFloats;
+    const double a = pow(1.0 / q[3], kP), b = pow(1.0 / q[4], kP), c = pow(1.0 / q[5], kP);
+    total += pow((a * b + a * c + b * c) / 3.0, 1.0 / kP);
+  }
+  double acc = 0.0;
+  for (int k = 0; k < n_prims; ++k) {
+    const float* q = prims + (int64_t)k * kPrimFloats;
+    const double a = pow(1.0 / q[3], kP), b = pow(1.0 / q[4], kP), c = pow(1.0 / q[5], kP);
+    acc += pow((a * b + a * c + b * c) / 3.0, 1.0 / kP);
+    cdf[k] = k == n_prims - 1 ? 1.f : (float)(acc / total);
+  }
+}
+
+// |R^T (x - c) / a|^2 - 1 (negative strictly inside).
+__device__ __forceinline__ float prim_implicit(const float* q, float x0, float x1, float x2) {
+  const float r0 = x0 - q[0], r1 = x1 - q[1], r2 = x2 - q[2];
+  const float l0 = (q[6] * r0 + q[7] * r1 + q[8] * r2) * q[3];
+  const float l1 = (q[9] * r0 + q[10] * r1 + q[11] * r2) * q[4];
+  const float l2 = (q[12] * r0 + q[13] * r1 + q[14] * r2) * q[5];
+  return l0 * l0 + l1 * l1 + l2 * l2 - 1.f;
+}
+
+__device__ __forceinline__ void sphere_pt(float u1, float u2, float& s0, float& s1, float& s2) {
+  const float z = 1.f - 2.f * u1;
+  const float r = sqrtf(fmaxf(0.f, 1.f - z * z));
+  float sn, cs;
+  sincospif(2.f * u2, &sn, &cs);
+  s0 = r * cs; s1 = r * sn; s2 = z;
+}
+
+// One ray per thread from uniforms u [3 tries + 2][n]: candidate j uses rows 3j .. 3j + 2, the
+// direction the last two rows.  Surface rays: primitive k by binary search in the cumulative
+// area weights, point c + R (a s), normal R (s / a); rejected when strictly inside another
+// primitive.  Free rays: origin in the box, rejected when strictly inside any primitive.
+// The last candidate is kept when every one was rejected.
+__global__ __launch_bounds__(kShadeThreads) void sample_kernel(const float* __restrict__ prims,
+                                                               const float* __restrict__ cdf, int n_prims,
+                                                               const float* __restrict__ u, int64_t n, int mode,
+                                                               float box_half, float offset, int tries,
+                                                               float* __restrict__ rays) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool surf = mode == 0 || (mode == 2 && (i & 1) == 0 && i < 2 * (n / 2));
+  float o0 = 0.f, o1 = 0.f, o2 = 0.f;
+  for (int j = 0; j < tries; ++j) {
+    const float ua = u[(3 * j) * n + i], ub = u[(3 * j + 1) * n + i], uc = u[(3 * j + 2) * n + i];
+    float x0, x1, x2, c0, c1, c2;
+    int k = -1;
+    if (surf) {
+      int lo = 0, hi = n_prims - 1;   // first index whose weight exceeds ua
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf[mid] > ua) hi = mid; else lo = mid + 1;
+      }
+      k = lo;
+      const float* q = prims + (int64_t)k * kPrimFloats;
+      float s0, s1, s2;
+      sphere_pt(ub, uc, s0, s1, s2);
+      const float a0 = 1.f / q[3], a1 = 1.f / q[4], a2 = 1.f / q[5];
+      // R v = sum_row (R^T)[row][m] v_row
+      const float v0 = a0 * s0, v1 = a1 * s1, v2 = a2 * s2;
+      x0 = q[0] + q[6] * v0 + q[9] * v1 + q[12] * v2;
+      x1 = q[1] + q[7] * v0 + q[10] * v1 + q[13] * v2;
+      x2 = q[2] + q[8] * v0 + q[11] * v1 + q[14] * v2;
+      const float w0 = s0 * q[3], w1 = s1 * q[4], w2 = s2 * q[5];
+      float n0 = q[6] * w0 + q[9] * w1 + q[12] * w2;
+      float n1 = q[7] * w0 + q[10] * w1 + q[13] * w2;
+      float n2 = q[8] * w0 + q[11] * w1 + q[14] * w2;
+      const float nn = 1.f / sqrtf(n0 * n0 + n1 * n1 + n2 * n2);
+      c0 = x0 + offset * (n0 * nn); c1 = x1 + offset * (n1 * nn); c2 = x2 + offset * (n2 * nn);
+    } else {
+      x0 = -box_half + 2.f * box_half * ua;
+      x1 = -box_half + 2.f * box_half * ub;
+      x2 = -box_half + 2.f * box_half * uc;
+      c0 = x0; c1 = x1; c2 = x2;
+    }
+    bool inside = false;
+    for (int m = 0; m < n_prims && !inside; ++m)
+      inside = m != k && prim_implicit(prims + (int64_t)m * kPrimFloats, x0, x1, x2) < 0.f;
+    o0 = c0; o1 = c1; o2 = c2;
+    if (!inside) break;
+  }
+  float d0, d1, d2;
+  sphere_pt(u[(3 * tries) * n + i], u[(3 * tries + 1) * n + i], d0, d1, d2);
+  rays[i] = o0; rays[n + i] = o1; rays[2 * n + i] = o2;
+  rays[3 * n + i] = d0; rays[4 * n + i] = d1; rays[5 * n + i] = d2;
+}
+
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kShadeThreads - 1) / kShadeThreads); }
 
 }  // namespace
@@ -257,6 +354,26 @@ int ddf_shade(const float* t, const float* xi, const uint8_t* ray_hit, const flo
                                                                           light[1], light[2], n_ao, offset, ao_radius,
                                                                           shadow, ao);
   return hip_status(hipGetLastError(), "ddf_shade launch");
+}
+
+int ddf_sample_rays(const float* prims, int32_t n_prims, const float* u, int64_t n, int32_t mode, float box_half,
+                    float offset, int32_t tries, float* cdf_ws, float* rays, void* stream) {
+  int rc;
+  if (n_prims < 1) return fail(DDF_ERR_INVALID_ARG, "n_prims must be >= 1");
+  if (n < 0 || n > (int64_t)INT32_MAX / 32) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (mode < 0 || mode > 2) return fail(DDF_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
+  if (tries < 1 || tries > 16) return fail(DDF_ERR_INVALID_ARG, "tries must be in 1..16");
+  if (!(box_half > 0.f) || !(offset >= 0.f)) return fail(DDF_ERR_INVALID_ARG, "box_half <= 0 or offset < 0");
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(prims, "prims")) || (rc = check_ptr(u, "u")) || (rc = check_ptr(cdf_ws, "cdf_ws")) ||
+      (rc = check_ptr(rays, "rays")))
+    return rc;
+  g_err_clear();
+  hipStream_t st = (hipStream_t)stream;
+  area_cdf_kernel<<<1, 64, 0, st>>>(prims, n_prims, cdf_ws);
+  sample_kernel<<<grid_for(n), kShadeThreads, 0, st>>>(prims, cdf_ws, n_prims, u, n, mode, box_half, offset, tries,
+                                                       rays);
+  return hip_status(hipGetLastError(), "ddf_sample_rays launch");
 }
 
 }  // extern "C"

@@ -448,3 +448,15 @@ def scene_ground(n: int, seed: int) -> Scene:
     rots = _random_rotations(rng, n)
     rots[is_sphere] = np.eye(3)
     return Scene(c, axes, np.concatenate([np.eye(3)[None], rots]))
+
+
+def scene_object(n: int, seed: int) -> Scene:
+    """One compound object on the ground slab of scene_ground: n spheres and ellipsoids
+    (axes 0.15 .. 0.45) whose centres lie within 0.45 of (0, -0.45, 0), the way the paper's
+    fields each hold one normalised object."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = np.array([0.0, -0.45, 0.0]) + rng.uniform(-0.45, 0.45, (n, 3))
+    a = rng.uniform(0.15, 0.45, (n, 3))
+    rots = _random_rotations(rng, n)
+    return Scene(np.concatenate([[[0.0, -1.02, 0.0]], c]), np.concatenate([[[1.45, 0.02, 1.45]], a]),
+                 np.concatenate([np.eye(3)[None], rots]))

@@ -151,26 +151,32 @@ def test_reference_maps_match_oracle():
 
 
 def test_trained_hash_field_shading():
-    """End to end: the paper's hash-grid field distilled on the ground scene (recipe batches),
-    then the render's secondary rays answered by the field.  The field's maps equal the
-    oracle's reduction of the field's own answers, and track the reference maps."""
+    """End to end: the paper's hash-grid field distilled by its recipe (fresh GPU-sampled
+    batches of 16,384 rays, 30 % self-consistency points, cosine schedule; 3,000 steps here)
+    on one compound object above a ground slab, then the render's secondary rays answered by
+    the field.  The field's maps equal the oracle's reduction of the field's own answers and
+    track the reference maps (floors from a 3,000-step run with margin; the table gradient's
+    float atomics make runs differ slightly)."""
     dev = cuda()
-    sc = I.scene_ground(24, 5)
+    sc = I.scene_object(8, 5)
     desc = I.HASH_PAPER
     prims = _t(ddf.scene_prims(sc), dev)
     import oracle.hashgrid_oracle as H
     from oracle import ddf_oracle as O
     p = _t(I.hash_params(desc, H.table_entries(desc), 46), dev)
     m = torch.zeros_like(p); vv = torch.zeros_like(p)
-    B = 16384
+    B, T = 16384, 4
     ws = torch.empty(ddf.hash_train_workspace_bytes(desc, B), dtype=torch.uint8, device=dev)
-    pool = [_t(I.train_rays(sc, B, 4700 + j), dev) for j in range(8)]
-    steps = 600
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(48)
+    U = torch.empty((3 * T + 2, B), device=dev)
+    steps = 3000
     for s in range(1, steps + 1):
-        rays = pool[s % len(pool)]
+        U.uniform_(generator=gen)
+        rays = ddf.sample_rays(prims, U, mode=2, offset=OFF)
         t, h = ddf.cast_targets(prims, rays)
         t = torch.where(h > 0, t, torch.zeros_like(t))
-        rs, ts, hs = ddf.shift_rays(rays, t, h, _t(I.uniforms(3, B, 4800 + s), dev), 0.3)
+        rs, ts, hs = ddf.shift_rays(rays, t, h, torch.rand((3, B), device=dev, generator=gen), 0.3)
         hp = ddf.TrainHParamsC(ddf.lr_cosine(s - 1, total=steps), 0.9, 0.999, 1e-8, O.BCE_WEIGHT, O.L1_CLAMP, s)
         ddf.hash_train_step(desc, p, m, vv, rs, ts, hs, hp, ws)
     v = _view(128, 128)
@@ -197,7 +203,4 @@ def test_trained_hash_field_shading():
     ma = S.mae(ao.cpu().numpy(), aor.cpu().numpy(), hm)
     print(f"trained hash field ({steps} steps): shadow PSNR {ps:.2f} dB, AO PSNR {pa:.2f} dB, AO MAE {ma:.4f}; "
           f"shadowed {shr.cpu().numpy()[hm].mean():.3f}, mean AO {aor.cpu().numpy()[hm].mean():.3f}")
-    # a constant map (no shadow, no occlusion) as the floor the field must clear
-    zero = np.zeros(P)
-    assert ps > S.psnr(zero, shr.cpu().numpy(), hm) + 3.0
-    assert ma < S.mae(zero, aor.cpu().numpy(), hm)
+    assert ps > 9.0 and pa > 18.0 and ma < 0.06
