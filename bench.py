@@ -11,8 +11,10 @@ rays; distillation training steps (65,536 rays through the 12 x 1024 net, and
 262,144 rays through the 16 x 1024 net with activations recomputed every 4
 layers, bf16 and fp32 each); and sphere tracing of a signed-distance MLP of the
 same size along the same rays (the paper's baseline); and the paper's own 52 MB hash-grid
-field, queried at 1K to 2^20 rays and trained on 16,384-ray batches.  The float64 oracle is
-timed on the host cores over a bounded sample of the same rays.
+field, queried at 1K to 2^20 rays and trained on 16,384-ray batches; and that field,
+distilled by the paper's recipe on one object above a ground slab, answering a 512 x 512
+frame's shadow and AO rays (maps against exact casting).  The float64 oracle is timed on the
+host cores over a bounded sample of the same rays.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16]
 """
@@ -39,9 +41,10 @@ N_RAYS = 1 << 20
 # files the bench reports null until the counters are taken again.
 COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 TRAFFIC_KIB = {
-    "bf16": {"FETCH_SIZE": 5925032, "WRITE_SIZE": 8192,
-             "sha256": "6f15d0e0b63773c5d49a6062fb599a1ca37a46420f8ca63324ce49346521ea11"},
-    "fp8": {"FETCH_SIZE": 1625817, "WRITE_SIZE": 329993, "sha256": None},
+    "bf16": {"FETCH_SIZE": 5925033, "WRITE_SIZE": 8192,
+             "sha256": "439fb400e43d5295381397c33c0c19e59a467b2b043bf0249a40ecff96a16f51"},
+    "fp8": {"FETCH_SIZE": 1552400, "WRITE_SIZE": 61710,
+            "sha256": "acb00b46490c40646f485a71af6860aefd2eedaaadbc56b6b8c75b365315fb92"},
 }
 KERNEL_SOURCES = {
     "fp32": ["ddf_fwd.hip", "ddf_chain.h", "ddf_fwd.h", "ddf_internal.h"],
@@ -91,8 +94,9 @@ class KernelTimer:
         return e0.elapsed_time(e1) / reps
 
 
-def cpu_oracle_baseline(desc, params, rays_np, budget_s=12.0):
-    """The float64 oracle on a bounded sample of the same rays (rank 0, N = 1)."""
+def cpu_oracle_baseline(desc, params, rays_np, answers, budget_s=12.0):
+    """The float64 oracle on a bounded sample of the same rays (rank 0, N = 1); its answers
+    also give each precision's |dt| and flip rate against float64 on that sample."""
     from oracle import ddf_oracle as O
     try:
         from threadpoolctl import threadpool_info
@@ -106,23 +110,24 @@ def cpu_oracle_baseline(desc, params, rays_np, budget_s=12.0):
     n = int(min(rays_np.shape[1], max(probe, probe * budget_s / max(dt, 1e-6))))
     n = max(probe, n // probe * probe)
     t0 = time.perf_counter()
-    O.ddf_query(desc, params, rays_np[:, :n])
+    t64, x64, _, _ = O.ddf_query(desc, params, rays_np[:, :n])
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "rays/s", "cores": int(threads), "kind": "oracle",
             "sample": f"first {n} of the {rays_np.shape[1]} shadow rays, float64 numpy forward "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s)",
+            "precision_vs_float64": {p: dt_stats(t64, x64, t[:n], xi[:n]) for p, (t, xi) in answers.items()}}
 
 
-def precision_stats(desc, params, rays_np, t, xi, sample=2048):
-    """max/mean |dt| and visibility flip rate against the float64 oracle on a strided sample."""
-    from oracle import ddf_oracle as O
-    idx = np.linspace(0, rays_np.shape[1] - 1, sample).astype(np.int64)
-    t64, x64, _, _ = O.ddf_query(desc, params, rays_np[:, idx])
-    tt = t[idx].astype(np.float64)
-    xx = xi[idx].astype(np.float64)
-    d = np.abs(tt - t64)
+def dt_stats(t_ref, x_ref, t, xi):
+    """max/mean |dt| and visibility flip rate (xi > 0.5) of answers against reference answers."""
+    d = np.abs(np.asarray(t, dtype=np.float64) - np.asarray(t_ref, dtype=np.float64))
     return {"max_abs_dt": float(d.max()), "mean_abs_dt": float(d.mean()),
-            "flip_rate": float(((xx > 0.5) != (x64 > 0.5)).mean()), "sample": int(sample)}
+            "flip_rate": float(((np.asarray(xi) > 0.5) != (np.asarray(x_ref) > 0.5)).mean()), "rays": int(d.size)}
+
+
+def progress(msg):
+    """One line per finished leg on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -131,8 +136,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--legs", default="precisions,train,train_large,trace,hash,cpu",
-                    help="comma list of extra legs: precisions, train, train_large, trace, hash, cpu, copy")
+    ap.add_argument("--legs", default="precisions,train,train_large,trace,hash,shade,cpu",
+                    help="comma list of extra legs: precisions, train, train_large, trace, hash, shade, cpu, copy")
+    ap.add_argument("--shade-steps", type=int, default=30000,
+                    help="recipe steps of the hash-grid field trained for the shade leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
@@ -202,35 +209,50 @@ def main():
                      "kernel": f"fwd_kernel ({prec}), one launch per step",
                      "flop_per_launch": fpr * N_RAYS},
     }
-    out["precision_stats"] = {prec: precision_stats(desc, params_np, rays_np, t_h, xi_h)}
-
+    answers = {prec: (t_h, xi_h)}
+    others = ("fp32", "bf16", "fp8") if "precisions" in legs else ("fp32",)
+    res = {}
+    for p in others:
+        if p == prec:
+            continue
+        steps = 3 if p == "fp32" else max(3, args.steps // 2)
+        msp, tp, xp = run_query(p, steps, 1)
+        answers[p] = (tp, xp)
+        tf = fpr * N_RAYS / (msp * 1e-3) / 1e12
+        res[p] = {"rays_per_s": N_RAYS / (msp * 1e-3), "ms": msp, "tflops": tf, "frac": tf / PEAK_TFLOPS[p]}
+    # the precision cost: every reduced-precision answer against the fp32 query, all 2^20 rays
+    t32, x32 = answers["fp32"]
+    out["precision_stats"] = {prec: dt_stats(t32, x32, t_h, xi_h) if prec != "fp32" else None}
+    for p in res:
+        if p != "fp32":
+            res[p].update(dt_stats(t32, x32, *answers[p]))
     if "precisions" in legs:
-        res = {}
-        for p in ("fp32", "bf16", "fp8"):
-            if p == prec:
-                continue
-            steps = 3 if p == "fp32" else max(3, args.steps // 2)
-            msp, tp, xp = run_query(p, steps, 1)
-            tf = fpr * N_RAYS / (msp * 1e-3) / 1e12
-            res[p] = {"rays_per_s": N_RAYS / (msp * 1e-3), "ms": msp, "tflops": tf,
-                      "frac": tf / PEAK_TFLOPS[p], **precision_stats(desc, params_np, rays_np, tp, xp)}
         out["precisions"] = res
 
+    progress(f"queries done ({prec} {ms:.2f} ms/step)")
     if "train" in legs:
         out["train"] = train_leg(torch, ddf, I, dev, timer, args.steps)
+        progress("train leg done")
 
     if "train_large" in legs:
         out["train_large"] = train_leg(torch, ddf, I, dev, timer, 4, batch=1 << 18, desc=I.NET_LARGE,
                                        recompute_every=4, seed=1300, lr=3e-4)
+        progress("train_large leg done")
 
     if "trace" in legs:
         out["sphere_trace"] = trace_leg(torch, ddf, I, dev, rays, timer, out, scene)
+        progress("trace leg done")
 
     if "hash" in legs:
         out["hash_grid"] = hash_leg(torch, ddf, I, dev, rays, timer, args.steps)
+        progress("hash leg done")
+
+    if "shade" in legs:
+        out["shading"] = shade_leg(torch, ddf, I, dev, timer, args.shade_steps)
+        progress("shade leg done")
 
     if "cpu" in legs:
-        out["cpu_baseline"] = cpu_oracle_baseline(desc, params_np, rays_np)
+        out["cpu_baseline"] = cpu_oracle_baseline(desc, params_np, rays_np, answers)
     out["wall_s_timed"] = wall
     print(json.dumps(out))
 
@@ -341,6 +363,81 @@ def hash_leg(torch, ddf, I, dev, rays, timer, steps):
     res["train"] = {"batch": B, "ms_per_step": ms, "train_rays_per_s": B / (ms * 1e-3), "loss_first": l0,
                     "loss_last": float(loss[0].item()), "steps": step[0], "skipped": int(flag[0].item())}
     return res
+
+
+def shade_leg(torch, ddf, I, dev, timer, steps):
+    """The renderer's use of the field (shadows and AO, the paper's Table VI analogue): the
+    paper's hash-grid field distilled by its recipe (`steps` steps of 16,384 fresh GPU-sampled
+    rays, 30 % self-consistency points, cosine lr from 3e-3 to 5 %) on one compound object
+    above a ground slab; then one timed 512 x 512 frame: G-buffer from the exact scene, one
+    shadow ray and 16 cosine-weighted AO rays per pixel, the field's answers (two-pass
+    hash query), the per-pixel maps.  Quality against the same rays cast exactly."""
+    import time
+    sc = I.scene_object(8, 5)
+    desc = I.HASH_PAPER
+    prims = torch.from_numpy(ddf.scene_prims(sc)).to(dev)
+    n_entries = sum(ddf.hash_level(desc, l)[1] for l in range(desc.n_levels))
+    p = torch.from_numpy(I.hash_params(desc, n_entries, 46)).to(dev)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    B, T = 16384, 4
+    ws = torch.empty(ddf.hash_train_workspace_bytes(desc, B), dtype=torch.uint8, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(48)
+    U = torch.empty((3 * T + 2, B), device=dev)
+    U3 = torch.empty((3, B), device=dev)
+    loss = torch.empty(4, dtype=torch.float32, device=dev)
+    flag = torch.empty(4, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(1, steps + 1):
+        U.uniform_(generator=gen)
+        U3.uniform_(generator=gen)
+        rays = ddf.sample_rays(prims, U, mode=2, offset=I.NORMAL_OFFSET)
+        t, h = ddf.cast_targets(prims, rays)
+        t = torch.where(h > 0, t, torch.zeros_like(t))
+        rs, ts, hs = ddf.shift_rays(rays, t, h, U3, 0.3)
+        hp = ddf.TrainHParamsC(ddf.lr_cosine(st - 1, total=steps), 0.9, 0.999, 1e-8, 0.3, 3.0, st)
+        ddf.hash_train_step(desc, p, m, v, rs, ts, hs, hp, ws, loss_out=loss, flag=flag)
+        if st % 10000 == 0:
+            torch.cuda.synchronize()
+            progress(f"shade leg: {st} of {steps} training steps")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    view = I.View()
+    K = I.AO_RAYS
+    P = view.width * view.height
+    u = torch.from_numpy(I.uniforms(2, P * K, 47)).to(dev)
+    rays = torch.empty((6, P * (1 + K)), dtype=torch.float32, device=dev)
+    qws = torch.empty(ddf.hash_query_workspace_bytes(desc, P * (1 + K)), dtype=torch.uint8, device=dev)
+    res = {}
+
+    def frame():
+        gb, hit = ddf.primary_gbuffer(view, prims)
+        ddf.secondary_rays(gb, hit, I.SHADE_LIGHT, K, u, I.NORMAL_OFFSET, out=rays)
+        tf, xf = ddf.hash_query(desc, p, rays, ws=qws)
+        sh, ao = ddf.shade(tf, gb, hit, I.SHADE_LIGHT, K, I.NORMAL_OFFSET, xi=xf)
+        res.update(gb=gb, hit=hit, sh=sh, ao=ao)
+    for _ in range(2):
+        frame()
+    torch.cuda.synchronize()
+    ms = timer.time(frame, 10)
+    tg, rh = ddf.cast_targets(prims, rays)
+    shr, aor = ddf.shade(tg, res["gb"], res["hit"], I.SHADE_LIGHT, K, I.NORMAL_OFFSET, ray_hit=rh)
+    torch.cuda.synchronize()
+    hm = res["hit"].cpu().numpy().astype(bool)
+    sh, ao, shr, aor = (x.cpu().numpy().astype(np.float64)[hm] for x in (res["sh"], res["ao"], shr, aor))
+
+    def psnr(a, b):
+        mse = float(np.mean((a - b) ** 2))
+        return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
+    n_rays = P * (1 + K)
+    return {"scene": "compound object of 8 ellipsoids on a ground slab", "train_steps": steps, "train_batch": B,
+            "train_s": train_s, "train_ms_per_step": train_s * 1e3 / steps, "final_loss": float(loss[0].item()),
+            "frame": f"{view.width}x{view.height}, 1 shadow + {K} AO rays per pixel", "frame_ms": ms,
+            "secondary_rays": n_rays, "secondary_rays_per_s": n_rays / (ms * 1e-3),
+            "pixels_hit": int(hm.sum()), "shadow_psnr_db": psnr(sh, shr), "ao_psnr_db": psnr(ao, aor),
+            "ao_mae": float(np.mean(np.abs(ao - aor))), "paper_table6": {"shadow_psnr_db": 30.3, "ao_psnr_db": 21.3}}
 
 
 def fit_sdf(torch, ddf, I, dev, scene, steps=400, batch=65536, prec="bf16", seed=100):
