@@ -376,6 +376,7 @@ def shade_leg(torch, ddf, I, dev, timer, steps):
     sc = I.scene_object(8, 5)
     desc = I.HASH_PAPER
     prims = torch.from_numpy(ddf.scene_prims(sc)).to(dev)
+    cdf = ddf.prim_area_cdf(prims)
     n_entries = sum(ddf.hash_level(desc, l)[1] for l in range(desc.n_levels))
     p = torch.from_numpy(I.hash_params(desc, n_entries, 46)).to(dev)
     m = torch.zeros_like(p)
@@ -393,7 +394,7 @@ def shade_leg(torch, ddf, I, dev, timer, steps):
     for st in range(1, steps + 1):
         U.uniform_(generator=gen)
         U3.uniform_(generator=gen)
-        rays = ddf.sample_rays(prims, U, mode=2, offset=I.NORMAL_OFFSET)
+        rays = ddf.sample_rays(prims, U, mode=2, offset=I.NORMAL_OFFSET, cdf=cdf)
         t, h = ddf.cast_targets(prims, rays)
         t = torch.where(h > 0, t, torch.zeros_like(t))
         rs, ts, hs = ddf.shift_rays(rays, t, h, U3, 0.3)

@@ -337,10 +337,14 @@ int ddf_shade(const float* t, const float* xi, const uint8_t* ray_hit, const flo
  * rejected and the next candidate taken, up to `tries` (1..16; the last is kept).
  * Directions are uniform on the sphere.  u [3 tries + 2][n] device uniforms in [0, 1): rows
  * 3j .. 3j + 2 drive candidate j (primitive choice and sphere point, or x, y, z), the last
- * two the direction (z = 1 - 2 u, phi = 2 pi u').  cdf_ws: device scratch of n_prims floats
- * (overwritten with the cumulative area weights).  n <= 2^26. */
-int ddf_sample_rays(const float* prims, int32_t n_prims, const float* u, int64_t n, int32_t mode, float box_half,
-                    float offset, int32_t tries, float* cdf_ws, float* rays, void* stream);
+ * two the direction (z = 1 - 2 u, phi = 2 pi u').  cdf [n_prims]: the cumulative area
+ * weights from ddf_prim_area_cdf (once per scene).  n <= 2^26. */
+int ddf_sample_rays(const float* prims, int32_t n_prims, const float* cdf, const float* u, int64_t n, int32_t mode,
+                    float box_half, float offset, int32_t tries, float* rays, void* stream);
+
+/* Cumulative surface-area weights of the primitives, cdf [n_prims] (device), normalised to
+ * end at exactly 1 (computed in double). */
+int ddf_prim_area_cdf(const float* prims, int32_t n_prims, float* cdf, void* stream);
 
 #ifdef __cplusplus
 }

@@ -761,13 +761,19 @@ __global__ __launch_bounds__(kHT) void outer_reduce_kernel(const float* d, int l
   }
 }
 
-// out[k] = sum over blocks b (in order) of part[b][k].
+// out[k] = sum over blocks b of part[b][k], in a fixed order: eight running sums over
+// b = j (mod 8), then a pairwise tree of the eight (eight loads in flight per thread).
 __global__ void sum_parts_kernel(const float* part, int nblk, int stride, float* out) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= stride) return;
-  float s = 0.f;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * stride + k];
-  out[k] = s;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int b = 0;
+  for (; b + 8 <= nblk; b += 8) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] += part[(int64_t)(b + j) * stride + k];
+  }
+  for (int j = 0; b + j < nblk; ++j) s[j] += part[(int64_t)(b + j) * stride + k];
+  out[k] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 __global__ void fill_zero_kernel(float* p, int64_t n) {

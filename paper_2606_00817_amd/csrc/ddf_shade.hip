@@ -356,8 +356,17 @@ int ddf_shade(const float* t, const float* xi, const uint8_t* ray_hit, const flo
   return hip_status(hipGetLastError(), "ddf_shade launch");
 }
 
-int ddf_sample_rays(const float* prims, int32_t n_prims, const float* u, int64_t n, int32_t mode, float box_half,
-                    float offset, int32_t tries, float* cdf_ws, float* rays, void* stream) {
+int ddf_prim_area_cdf(const float* prims, int32_t n_prims, float* cdf, void* stream) {
+  int rc;
+  if (n_prims < 1) return fail(DDF_ERR_INVALID_ARG, "n_prims must be >= 1");
+  if ((rc = check_ptr(prims, "prims")) || (rc = check_ptr(cdf, "cdf"))) return rc;
+  g_err_clear();
+  area_cdf_kernel<<<1, 64, 0, (hipStream_t)stream>>>(prims, n_prims, cdf);
+  return hip_status(hipGetLastError(), "ddf_prim_area_cdf launch");
+}
+
+int ddf_sample_rays(const float* prims, int32_t n_prims, const float* cdf, const float* u, int64_t n, int32_t mode,
+                    float box_half, float offset, int32_t tries, float* rays, void* stream) {
   int rc;
   if (n_prims < 1) return fail(DDF_ERR_INVALID_ARG, "n_prims must be >= 1");
   if (n < 0 || n > (int64_t)INT32_MAX / 32) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
@@ -365,14 +374,12 @@ int ddf_sample_rays(const float* prims, int32_t n_prims, const float* u, int64_t
   if (tries < 1 || tries > 16) return fail(DDF_ERR_INVALID_ARG, "tries must be in 1..16");
   if (!(box_half > 0.f) || !(offset >= 0.f)) return fail(DDF_ERR_INVALID_ARG, "box_half <= 0 or offset < 0");
   if (n == 0) return DDF_OK;
-  if ((rc = check_ptr(prims, "prims")) || (rc = check_ptr(u, "u")) || (rc = check_ptr(cdf_ws, "cdf_ws")) ||
+  if ((rc = check_ptr(prims, "prims")) || (rc = check_ptr(cdf, "cdf")) || (rc = check_ptr(u, "u")) ||
       (rc = check_ptr(rays, "rays")))
     return rc;
   g_err_clear();
-  hipStream_t st = (hipStream_t)stream;
-  area_cdf_kernel<<<1, 64, 0, st>>>(prims, n_prims, cdf_ws);
-  sample_kernel<<<grid_for(n), kShadeThreads, 0, st>>>(prims, cdf_ws, n_prims, u, n, mode, box_half, offset, tries,
-                                                       rays);
+  sample_kernel<<<grid_for(n), kShadeThreads, 0, (hipStream_t)stream>>>(prims, cdf, n_prims, u, n, mode, box_half,
+                                                                        offset, tries, rays);
   return hip_status(hipGetLastError(), "ddf_sample_rays launch");
 }
 

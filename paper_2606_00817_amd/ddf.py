@@ -88,8 +88,9 @@ SIGNATURES = {
                                           ctypes.c_float, _P, _P]),
     "ddf_shade": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
                                  ctypes.c_float, ctypes.c_float, _P, _P, _P]),
-    "ddf_sample_rays": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
-                                       ctypes.c_int32, _P, _P, _P]),
+    "ddf_prim_area_cdf": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
+    "ddf_sample_rays": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _I64, ctypes.c_int32, ctypes.c_float,
+                                       ctypes.c_float, ctypes.c_int32, _P, _P]),
     "sdf_train_step": (ctypes.c_int, [_D, _P, _P, _P, _P, _P, _P, _I64, ctypes.POINTER(TrainHParamsC),
                                       _P, _P, _P, _P, _SZ, _P]),
 }
@@ -472,10 +473,19 @@ def shade(t: torch.Tensor, gbuf: torch.Tensor, hit: torch.Tensor, light, n_ao: i
     return shadow, ao
 
 
+def prim_area_cdf(prims: torch.Tensor) -> torch.Tensor:
+    """Cumulative surface-area weights of the primitives (once per scene)."""
+    _dev(prims, torch.float32, "prims")
+    cdf = torch.empty(max(1, prims.shape[0]), dtype=torch.float32, device=prims.device)
+    _check(lib().ddf_prim_area_cdf(_ptr(prims), prims.shape[0], _ptr(cdf), _stream()))
+    return cdf
+
+
 def sample_rays(prims: torch.Tensor, u: torch.Tensor, mode: int = 2, box_half: float = 1.5, offset: float = 1e-3,
-                tries: int | None = None, out: torch.Tensor | None = None):
+                tries: int | None = None, out: torch.Tensor | None = None, cdf: torch.Tensor | None = None):
     """Training rays [6][n] from uniforms u [3 tries + 2][n] (see ddf_sample_rays); mode 0
-    surface, 1 free, 2 mixed (surface at even positions)."""
+    surface, 1 free, 2 mixed (surface at even positions).  cdf: prim_area_cdf(prims), computed
+    here when not given."""
     _dev(prims, torch.float32, "prims")
     _dev(u, torch.float32, "u")
     T = (u.shape[0] - 2) // 3 if tries is None else tries
@@ -483,7 +493,8 @@ def sample_rays(prims: torch.Tensor, u: torch.Tensor, mode: int = 2, box_half: f
         raise DDFError(f"u needs 3 tries + 2 = {3 * T + 2} rows, has {u.shape[0]}")
     n = u.shape[1]
     rays = out if out is not None else torch.empty((6, n), dtype=torch.float32, device=u.device)
-    cdf = torch.empty(max(1, prims.shape[0]), dtype=torch.float32, device=u.device)
-    _check(lib().ddf_sample_rays(_ptr(prims), prims.shape[0], _ptr(u), n, int(mode), float(box_half), float(offset),
-                                 int(T), _ptr(cdf), _ptr(rays), _stream()))
+    cdf = prim_area_cdf(prims) if cdf is None else cdf
+    _dev(cdf, torch.float32, "cdf")
+    _check(lib().ddf_sample_rays(_ptr(prims), prims.shape[0], _ptr(cdf), _ptr(u), n, int(mode), float(box_half),
+                                 float(offset), int(T), _ptr(rays), _stream()))
     return rays

@@ -170,10 +170,11 @@ def test_trained_hash_field_shading():
     gen = torch.Generator(device=dev)
     gen.manual_seed(48)
     U = torch.empty((3 * T + 2, B), device=dev)
+    cdf = ddf.prim_area_cdf(prims)
     steps = 3000
     for s in range(1, steps + 1):
         U.uniform_(generator=gen)
-        rays = ddf.sample_rays(prims, U, mode=2, offset=OFF)
+        rays = ddf.sample_rays(prims, U, mode=2, offset=OFF, cdf=cdf)
         t, h = ddf.cast_targets(prims, rays)
         t = torch.where(h > 0, t, torch.zeros_like(t))
         rs, ts, hs = ddf.shift_rays(rays, t, h, torch.rand((3, B), device=dev, generator=gen), 0.3)
