@@ -392,15 +392,19 @@ def hash_query_workspace_bytes(desc, n) -> int:
     return int(lib().ddf_hash_query_workspace_bytes(ctypes.byref(d), int(n)))
 
 
-def hash_query(desc, params: torch.Tensor, rays: torch.Tensor, ws: torch.Tensor | None = None, fused: bool = False):
+def hash_query(desc, params: torch.Tensor, rays: torch.Tensor, ws: torch.Tensor | None = None, fused: bool = False,
+               t: torch.Tensor | None = None, xi: torch.Tensor | None = None):
     """(t, xi) of rays [6][n].  fused=True: the one-kernel path; else the two-pass path through
-    `ws` (allocated here when not given)."""
+    `ws` (allocated here when not given).  t, xi: output tensors to fill (allocated when not
+    given); with both outputs and ws given the call allocates nothing (graph capture)."""
     _dev(params, torch.float32, "params")
     _dev(rays, torch.float32, "rays")
     d = hash_desc_c(desc)
     n = rays.shape[1]
-    t = torch.empty(n, dtype=torch.float32, device=rays.device)
-    xi = torch.empty(n, dtype=torch.float32, device=rays.device)
+    t = torch.empty(n, dtype=torch.float32, device=rays.device) if t is None else t
+    xi = torch.empty(n, dtype=torch.float32, device=rays.device) if xi is None else xi
+    _dev(t, torch.float32, "t")
+    _dev(xi, torch.float32, "xi")
     if not fused and ws is None and n > 0:
         ws = torch.empty(hash_query_workspace_bytes(desc, n), dtype=torch.uint8, device=rays.device)
     wp, wb = (None, 0) if fused or ws is None else (_ptr(ws), ws.numel() * ws.element_size())
