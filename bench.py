@@ -316,7 +316,8 @@ def hash_leg(torch, ddf, I, dev, rays, timer, steps):
     100K and 2^20 rays (the ray counts of the paper's latency table), and distillation steps of
     16,384 rays (the paper's batch) against exact ray-cast targets of 1,024 ellipsoids.
     Both query paths are timed: two-pass (lookups with level groups pinned to XCDs, then the
-    MLP) and fused (one kernel).  Algorithmic bytes per queried ray: the ray (24 B), both
+    MLP) and fused (one kernel); and the two-pass path reading a float16 copy of the table
+    (the paper's reduced-precision inference setting).  Algorithmic bytes per queried ray: the ray (24 B), both
     outputs (8 B) and 16 levels x 8 corners x 2 float32 features gathered (1,024 B)."""
     desc = I.HASH_PAPER
     n_par = ddf.hash_param_count(desc)
@@ -326,6 +327,7 @@ def hash_leg(torch, ddf, I, dev, rays, timer, steps):
     res = {"field": "hash grid 16 x 2^19 x 2, 4 bands, 2x64 MLP", "params": n_par,
            "bytes": 4 * n_par, "algorithmic_bytes_per_ray": bpr, "query": {}}
     ws = torch.empty(ddf.hash_query_workspace_bytes(desc, rays.shape[1]), dtype=torch.uint8, device=dev)
+    table16 = ddf.hash_table_f16(desc, params)
     for n in (1000, 10000, 100000, rays.shape[1]):
         r = rays[:, :n].contiguous()
         row = {}
@@ -337,6 +339,14 @@ def hash_leg(torch, ddf, I, dev, rays, timer, steps):
             ms = timer.time(lambda: ddf.hash_query(desc, params, r, **kw), max(10, steps))
             row[path] = {"ms": ms, "rays_per_s": n / (ms * 1e-3), "us_per_ray": ms * 1e3 / n,
                          "gathered_GBps": bpr * n / (ms * 1e-3) / 1e9}
+        # the reduced-precision lookups (float16 table copy)
+        tq = torch.empty(n, dtype=torch.float32, device=dev)
+        xq = torch.empty(n, dtype=torch.float32, device=dev)
+        for _ in range(3):
+            ddf.hash_query_f16(desc, params, table16, r, ws=ws, t=tq, xi=xq)
+        torch.cuda.synchronize()
+        ms = timer.time(lambda: ddf.hash_query_f16(desc, params, table16, r, ws=ws, t=tq, xi=xq), max(10, steps))
+        row["two_pass_f16_table"] = {"ms": ms, "rays_per_s": n / (ms * 1e-3), "us_per_ray": ms * 1e3 / n}
         if n <= 100000:
             # the sparse regime: the two-pass query captured once, replayed (no host launch cost)
             tq = torch.empty(n, dtype=torch.float32, device=dev)

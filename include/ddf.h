@@ -274,6 +274,17 @@ size_t ddf_hash_query_workspace_bytes(const ddf_hash_desc* desc, int64_t n);
 int ddf_hash_query(const ddf_hash_desc* desc, const float* params, const float* rays, int64_t n,
                    float* t, float* xi, void* ws, size_t ws_bytes, void* stream);
 
+/* The reduced-precision query (Sec. III-C: inference runs in reduced precision): a float16
+ * copy of the table, round to nearest even, [entries][2] (ddf_hash_table_f16_bytes bytes,
+ * device), made after each change to params; the lookups read it (half the bytes and cache
+ * lines of the float32 table), the interpolation and the MLP stay float32.  Results equal
+ * the float32 query's on a table rounded to float16.  Two-pass only: ws as for
+ * ddf_hash_query, required. */
+size_t ddf_hash_table_f16_bytes(const ddf_hash_desc* desc);
+int ddf_hash_table_to_f16(const ddf_hash_desc* desc, const float* params, void* table16, void* stream);
+int ddf_hash_query_f16(const ddf_hash_desc* desc, const float* params, const void* table16, const float* rays,
+                       int64_t n, float* t, float* xi, void* ws, size_t ws_bytes, void* stream);
+
 /* One distillation step of the hash-grid field: forward, the loss of ddf_train_step,
  * backward (the table gradient gathered with float atomics: its summation order is not
  * fixed; every other reduction is), Adam over all parameters (skipped on a non-finite

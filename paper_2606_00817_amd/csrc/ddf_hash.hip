@@ -17,6 +17,8 @@
 
 #include <algorithm>
 
+#include <hip/hip_fp16.h>
+
 #include "ddf_chain.h"
 #include "ddf_internal.h"
 #include "ddf_train.h"
@@ -296,6 +298,7 @@ struct HashArgs {
   float* deltas;          // [n_hidden][R][64]: dL/da of each hidden layer
   float* gtab;            // table gradient [entries][2] (atomics)
   int64_t R;
+  const __half* table16;  // float16 copy of the table for the reduced-precision lookups
 };
 
 template <int NL, int NB, int NH>
@@ -355,7 +358,28 @@ __device__ __forceinline__ int grp_level(int g, int slot) {
 }
 
 // G[g][r] (16 bytes): the features of group g's levels for ray r, in slot order.
-template <int NL>
+// Table entries (2 features) of either storage type, as float2: one entry, or the pair at
+// entries i and i + 1 in one load (16 bytes for float32, 8 for float16; 4-byte aligned).
+__device__ __forceinline__ float2 entry1(const float* b, uint32_t i) {
+  return *reinterpret_cast<const float2*>(b + 2 * (size_t)i);
+}
+__device__ __forceinline__ void entry2(const float* b, uint32_t i, float2& e0, float2& e1) {
+  const f32x4 q = *reinterpret_cast<const f32x4*>(b + 2 * (size_t)i);
+  e0 = float2{q[0], q[1]};
+  e1 = float2{q[2], q[3]};
+}
+__device__ __forceinline__ float2 entry1(const __half* b, uint32_t i) {
+  return __half22float2(*reinterpret_cast<const __half2*>(b + 2 * (size_t)i));
+}
+__device__ __forceinline__ void entry2(const __half* b, uint32_t i, float2& e0, float2& e1) {
+  const uint2 q = *reinterpret_cast<const uint2*>(b + 2 * (size_t)i);
+  e0 = __half22float2(__builtin_bit_cast(__half2, q.x));
+  e1 = __half22float2(__builtin_bit_cast(__half2, q.y));
+}
+
+// G[g][r] (16 bytes): the features of group g's levels for ray r, in slot order.  TE: the
+// table's storage type (float, or the float16 copy of the reduced-precision query).
+template <int NL, typename TE>
 __global__ __launch_bounds__(kHT) void hash_pos_kernel(HashArgs a, float* G) {
   __shared__ LevelTab lt;
   stage_levels(a.L, lt);
@@ -368,7 +392,9 @@ __global__ __launch_bounds__(kHT) void hash_pos_kernel(HashArgs a, float* G) {
   for (int c = 0; c < 3; ++c) x[c] = a.rays[c * a.n + r];
   float p[3];
   unit_point(lt, x, p);
-  const float2* tab = reinterpret_cast<const float2*>(a.params);
+  const TE* table;
+  if constexpr (sizeof(TE) == 4) table = reinterpret_cast<const TE*>(a.params);
+  else table = reinterpret_cast<const TE*>(a.table16);
   float o[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int slot = 0; slot < 2; ++slot) {
@@ -378,13 +404,13 @@ __global__ __launch_bounds__(kHT) void hash_pos_kernel(HashArgs a, float* G) {
     float w[3];
     cell((float)lt.res[l], p, c, w);
     const uint32_t n1 = (uint32_t)lt.res[l] + 1u;
-    const float* base = a.params + 2 * lt.off[l];
+    const TE* base = table + 2 * lt.off[l];
     const bool dense = lt.dense[l];
     float f0 = 0.f, f1 = 0.f;
     // the 8 corners as 4 pairs along x, (v0, v1, v2) and (v0 + 1, v1, v2): densely indexed,
-    // the pair is 16 contiguous bytes; hashed, x enters the hash with multiplier 1, so for an
-    // even v0 the pair is the aligned 16 bytes {i & ~1, i | 1} and only an odd v0 needs a
-    // second load.  Products and sums in the same order as corner-by-corner.
+    // the pair is contiguous; hashed, x enters the hash with multiplier 1, so for an even v0
+    // the pair is the aligned {i & ~1, i | 1} and only an odd v0 needs a second load.
+    // Products and sums in the same order as corner-by-corner.
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const uint32_t v0 = c[0], v1 = c[1] + (m & 1), v2 = c[2] + (m >> 1);
@@ -392,22 +418,18 @@ __global__ __launch_bounds__(kHT) void hash_pos_kernel(HashArgs a, float* G) {
       const float wa = ((1.f - w[0]) * wy) * wz, wb = (w[0] * wy) * wz;
       float2 ca, cb;
       if (dense) {
-        const uint32_t i0 = v0 + n1 * (v1 + n1 * v2);
-        const f32x4 q = *reinterpret_cast<const f32x4*>(base + 2 * (size_t)i0);
-        ca = float2{q[0], q[1]};
-        cb = float2{q[2], q[3]};
+        entry2(base, v0 + n1 * (v1 + n1 * v2), ca, cb);
       } else {
         const uint32_t h = (v1 * kPrime1) ^ (v2 * kPrime2);
         const uint32_t i0 = (v0 ^ h) & lt.tmask;
-        const f32x4 q = *reinterpret_cast<const f32x4*>(base + 2 * (size_t)(i0 & ~1u));
+        float2 e0, e1;
+        entry2(base, i0 & ~1u, e0, e1);
         const bool odd = i0 & 1u;
-        ca = odd ? float2{q[2], q[3]} : float2{q[0], q[1]};
-        if (v0 & 1u) {
-          const uint32_t i1 = ((v0 + 1u) ^ h) & lt.tmask;
-          cb = *reinterpret_cast<const float2*>(base + 2 * (size_t)i1);
-        } else {
-          cb = odd ? float2{q[0], q[1]} : float2{q[2], q[3]};
-        }
+        ca = odd ? e1 : e0;
+        if (v0 & 1u)
+          cb = entry1(base, ((v0 + 1u) ^ h) & lt.tmask);
+        else
+          cb = odd ? e0 : e1;
       }
       f0 = fmaf(wa, ca.x, f0);
       f1 = fmaf(wa, ca.y, f1);
@@ -418,6 +440,12 @@ __global__ __launch_bounds__(kHT) void hash_pos_kernel(HashArgs a, float* G) {
     o[2 * slot + 1] = f1;
   }
   reinterpret_cast<f32x4*>(G)[g * a.n + r] = f32x4{o[0], o[1], o[2], o[3]};
+}
+
+// The float16 copy of the table (round to nearest even).
+__global__ void table_to_f16_kernel(const float* __restrict__ src, int64_t n, __half* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = __float2half_rn(src[i]);
 }
 
 // The MLP of the two-pass query on the matrix cores (fp32 32x32x2 MFMA), with the rays as the
@@ -820,9 +848,10 @@ bool hash_shape_supported(int nl, int nb, int nh) { return (nl == 16 || nl == 6)
 // G == nullptr: the fused one-kernel query; else the two-pass query through G
 // (kHGroups x n x 16 bytes).
 int run_hash_forward(const HashLayout& L, const float* params, const float* rays, int64_t n, int mode, float* o0,
-                     float* o1, float* G, hipStream_t st) {
+                     float* o1, float* G, hipStream_t st, const __half* table16 = nullptr) {
   HashArgs a{};
   a.L = L; a.params = params; a.rays = rays; a.n = n; a.mode = mode; a.out0 = o0; a.out1 = o1;
+  a.table16 = table16;
   const unsigned blocks = (unsigned)((n + kHT - 1) / kHT);
   if (G == nullptr) {
     if (L.n_levels == 16)
@@ -830,10 +859,16 @@ int run_hash_forward(const HashLayout& L, const float* params, const float* rays
     else
       hash_fwd_kernel<6, 4, 2><<<blocks, kHT, 0, st>>>(a);
   } else if (L.n_levels == 16) {
-    hash_pos_kernel<16><<<blocks * kHGroups, kHT, 0, st>>>(a, G);
+    if (table16)
+      hash_pos_kernel<16, __half><<<blocks * kHGroups, kHT, 0, st>>>(a, G);
+    else
+      hash_pos_kernel<16, float><<<blocks * kHGroups, kHT, 0, st>>>(a, G);
     hash_mlp_kernel<16, 4><<<blocks, kHT, 0, st>>>(a, G);
   } else {
-    hash_pos_kernel<6><<<blocks * kHGroups, kHT, 0, st>>>(a, G);
+    if (table16)
+      hash_pos_kernel<6, __half><<<blocks * kHGroups, kHT, 0, st>>>(a, G);
+    else
+      hash_pos_kernel<6, float><<<blocks * kHGroups, kHT, 0, st>>>(a, G);
     hash_mlp_kernel<6, 4><<<blocks, kHT, 0, st>>>(a, G);
   }
   return hip_status(hipGetLastError(), "hash forward launch");
@@ -908,6 +943,38 @@ int ddf_hash_query(const ddf_hash_desc* d, const float* params, const float* ray
   g_err_clear();
   return run_hash_forward(make_hash_layout(*d), params, rays, n, 0, t, xi, static_cast<float*>(ws),
                           (hipStream_t)stream);
+}
+
+size_t ddf_hash_table_f16_bytes(const ddf_hash_desc* d) {
+  if (check_hash_desc(d) != DDF_OK) return 0;
+  const HashLayout L = make_hash_layout(*d);
+  return (size_t)L.entries * 2 * sizeof(__half);
+}
+
+int ddf_hash_table_to_f16(const ddf_hash_desc* d, const float* params, void* table16, void* stream) {
+  int rc;
+  if ((rc = check_hash_desc(d))) return rc;
+  if ((rc = check_ptr(params, "params")) || (rc = check_ptr(table16, "table16"))) return rc;
+  g_err_clear();
+  const int64_t n = make_hash_layout(*d).entries * 2;
+  table_to_f16_kernel<<<2048, 256, 0, (hipStream_t)stream>>>(params, n, static_cast<__half*>(table16));
+  return hip_status(hipGetLastError(), "ddf_hash_table_to_f16 launch");
+}
+
+int ddf_hash_query_f16(const ddf_hash_desc* d, const float* params, const void* table16, const float* rays, int64_t n,
+                       float* t, float* xi, void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_hash_desc(d))) return rc;
+  if (n < 0 || n > (int64_t)INT32_MAX) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(params, "params")) || (rc = check_ptr(table16, "table16")) || (rc = check_ptr(rays, "rays")) ||
+      (rc = check_ptr(t, "t")) || (rc = check_ptr(xi, "xi")) || (rc = check_ptr(ws, "ws")))
+    return rc;
+  if (ws_bytes < (size_t)n * kHGroups * 16)
+    return fail(DDF_ERR_INVALID_ARG, "workspace %zu bytes < %zu", ws_bytes, (size_t)n * kHGroups * 16);
+  g_err_clear();
+  return run_hash_forward(make_hash_layout(*d), params, rays, n, 0, t, xi, static_cast<float*>(ws),
+                          (hipStream_t)stream, static_cast<const __half*>(table16));
 }
 
 size_t ddf_hash_train_workspace_bytes(const ddf_hash_desc* d, int64_t batch) {

@@ -80,6 +80,9 @@ SIGNATURES = {
                                       ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)]),
     "ddf_hash_query_workspace_bytes": (_SZ, [ctypes.POINTER(HashDescC), _I64]),
     "ddf_hash_query": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _I64, _P, _P, _P, _SZ, _P]),
+    "ddf_hash_table_f16_bytes": (_SZ, [ctypes.POINTER(HashDescC)]),
+    "ddf_hash_table_to_f16": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _P]),
+    "ddf_hash_query_f16": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _P, _I64, _P, _P, _P, _SZ, _P]),
     "ddf_hash_train_workspace_bytes": (_SZ, [ctypes.POINTER(HashDescC), _I64]),
     "ddf_hash_train_step": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _P, _P, _P, _P, _I64,
                                            ctypes.POINTER(TrainHParamsC), _P, _P, _P, _P, _SZ, _P]),
@@ -409,6 +412,35 @@ def hash_query(desc, params: torch.Tensor, rays: torch.Tensor, ws: torch.Tensor 
         ws = torch.empty(hash_query_workspace_bytes(desc, n), dtype=torch.uint8, device=rays.device)
     wp, wb = (None, 0) if fused or ws is None else (_ptr(ws), ws.numel() * ws.element_size())
     _check(lib().ddf_hash_query(ctypes.byref(d), _ptr(params), _ptr(rays), n, _ptr(t), _ptr(xi), wp, wb, _stream()))
+    return t, xi
+
+
+def hash_table_f16(desc, params: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """The float16 copy of the table (round to nearest even) for hash_query_f16."""
+    _dev(params, torch.float32, "params")
+    d = hash_desc_c(desc)
+    nb = int(lib().ddf_hash_table_f16_bytes(ctypes.byref(d)))
+    if nb == 0:
+        raise DDFError(f"unsupported hash-grid description: {lib().ddf_last_error().decode()}")
+    t16 = out if out is not None else torch.empty(nb // 2, dtype=torch.float16, device=params.device)
+    _check(lib().ddf_hash_table_to_f16(ctypes.byref(d), _ptr(params), _ptr(t16), _stream()))
+    return t16
+
+
+def hash_query_f16(desc, params: torch.Tensor, table16: torch.Tensor, rays: torch.Tensor,
+                   ws: torch.Tensor | None = None, t: torch.Tensor | None = None, xi: torch.Tensor | None = None):
+    """(t, xi) with the lookups reading the float16 table copy (two-pass path)."""
+    _dev(params, torch.float32, "params")
+    _dev(table16, torch.float16, "table16")
+    _dev(rays, torch.float32, "rays")
+    d = hash_desc_c(desc)
+    n = rays.shape[1]
+    t = torch.empty(n, dtype=torch.float32, device=rays.device) if t is None else t
+    xi = torch.empty(n, dtype=torch.float32, device=rays.device) if xi is None else xi
+    if ws is None:
+        ws = torch.empty(max(16, hash_query_workspace_bytes(desc, n)), dtype=torch.uint8, device=rays.device)
+    _check(lib().ddf_hash_query_f16(ctypes.byref(d), _ptr(params), _ptr(table16), _ptr(rays), n, _ptr(t), _ptr(xi),
+                                    _ptr(ws), ws.numel() * ws.element_size(), _stream()))
     return t, xi
 
 

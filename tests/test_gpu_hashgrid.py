@@ -85,6 +85,34 @@ def test_hash_query_2p20_paper_field():
     assert np.abs(xi[idx] - x64).max() <= 5e-6
 
 
+@pytest.mark.parametrize("desc", [I.HASH_SMALL, I.HASH_PAPER], ids=["6-level", "paper-16-level"])
+@pytest.mark.parametrize("n", [1000, 1])
+def test_hash_query_f16_matches_oracle(desc, n):
+    """The reduced-precision query (float16 table copy) against the oracle run on the table
+    rounded to float16 (numpy's round to nearest even), to the float32 query's bound; the copy
+    itself equals numpy's rounding bit for bit."""
+    dev = cuda()
+    params = _params(desc, 37)
+    sc = I.scene_mixed(256, 2)
+    rays = I.free_rays(sc, max(n, 8), 38)[:, :n]
+    if n >= 64:
+        rays = np.concatenate([rays[:, : n - 64], _edge_rays(desc, 64, 39)], axis=1)
+    pd = _t(params, dev)
+    t16 = ddf.hash_table_f16(desc, pd)
+    t, xi = ddf.hash_query_f16(desc, pd, t16, _t(rays, dev))
+    torch.cuda.synchronize()
+    E2 = H.table_entries(desc) * desc.n_feat
+    r16 = params[:E2].astype(np.float16)
+    assert np.array_equal(t16.cpu().numpy().view(np.uint16), r16.view(np.uint16))
+    p16 = params.astype(np.float64)
+    p16[:E2] = r16.astype(np.float64)
+    t64, x64, _, _ = H.hash_query(desc, p16, rays, coords="fp32")
+    dt = np.abs(t.cpu().numpy() - t64)
+    dx = np.abs(xi.cpu().numpy() - x64)
+    print(f"hash query f16 {desc.n_levels} levels n={n}: max |dt| {dt.max():.2e}, max |dxi| {dx.max():.2e}")
+    assert dt.max() <= 2e-5 * max(1.0, np.abs(t64).max()) and dx.max() <= 5e-6
+
+
 @pytest.mark.parametrize("desc,n", [(I.HASH_SMALL, 1000), (I.HASH_PAPER, 700)], ids=["6-level", "paper-16-level"])
 def test_hash_train_step_matches_oracle(desc, n):
     """Loss, gradient (table and MLP, per block) and the Adam update of one step against the
