@@ -136,8 +136,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--legs", default="precisions,train,train_large,trace,hash,shade,cpu",
-                    help="comma list of extra legs: precisions, train, train_large, trace, hash, shade, cpu, copy")
+    ap.add_argument("--legs", default="precisions,sparse,train,train_large,trace,hash,shade,cpu",
+                    help="comma list of extra legs: precisions, sparse, train, train_large, trace, hash, shade, "
+                         "cpu, copy")
     ap.add_argument("--shade-steps", type=int, default=30000,
                     help="recipe steps of the hash-grid field trained for the shade leg")
     args = ap.parse_args()
@@ -230,6 +231,26 @@ def main():
         out["precisions"] = res
 
     progress(f"queries done ({prec} {ms:.2f} ms/step)")
+    if "sparse" in legs:
+        # the sparse-query regime (the paper's 1K-100K ray counts): per-call time of the dense
+        # query in each reduced precision on the first n rays
+        sp = {}
+        for p in ("bf16", "fp8"):
+            pk = ddf.pack(desc, p, master, act_scales=scales if p == "fp8" else None)
+            dc = ddf.desc_c(desc, p)
+            row = {}
+            for n in (1000, 10000, 100000):
+                r = rays[:, :n].contiguous()
+                tq = torch.empty(n, dtype=torch.float32, device=dev)
+                xq = torch.empty(n, dtype=torch.float32, device=dev)
+                for _ in range(3):
+                    ddf.query_into(dc, pk, r, tq, xq)
+                torch.cuda.synchronize()
+                msn = timer.time(lambda: ddf.query_into(dc, pk, r, tq, xq), 20)
+                row[str(n)] = {"ms": msn, "rays_per_s": n / (msn * 1e-3), "us_per_ray": msn * 1e3 / n}
+            sp[p] = row
+        out["sparse_queries"] = sp
+        progress("sparse leg done")
     if "train" in legs:
         out["train"] = train_leg(torch, ddf, I, dev, timer, args.steps)
         progress("train leg done")
