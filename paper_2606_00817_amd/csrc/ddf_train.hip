@@ -369,7 +369,8 @@ struct DwArgs {
   int tiles_l0, tiles_l;  // workgroups for layer 1 (0 when it is not in this launch) and
                           // for every other hidden layer
   int tn_l0, tn_l;        // column tiles of layer 1 / of the other layers
-  int splits;             // ray ranges (blockIdx.y), each summed separately
+  int splits;             // ray ranges, each summed separately
+  int items;              // tiles x splits
 };
 
 // dW_l = sum_rays delta_l^T H_(l-1) (H_0 = the encoded features) and db_l = sum_rays delta_l,
@@ -378,6 +379,11 @@ struct DwArgs {
 // operands read in matrix-core order straight from the [R / 8][cols][8] stores through
 // buffer resources, three steps ahead in a ring of four.  Each (tile, range) sum has one
 // fixed order; with several ranges the partial sums are added in range order afterwards.
+// Work items (range, tile) go out in groups of four that share operand strips (a 2 x 2
+// block of tiles of one layer: two row strips of the deltas, two column strips of the
+// inputs), and a group's four workgroups get indices equal mod 8, so the dispatcher puts
+// them on one XCD, at the same time: the strips come from HBM once per group and the other
+// three reads hit that XCD's L2.
 template <class P, int TM, int TN>
 __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
   using Frag = typename P::AFrag;
@@ -386,7 +392,13 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
   constexpr int KB = P::KBLK;    // rays per step
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  int blk = blockIdx.x;
+  // block -> (group, member) -> work item (range, tile)
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int item = 4 * (8 * (slot >> 2) + xcd) + (slot & 3);
+  if (item >= a.items) return;   // whole workgroup, before any memory access
+  const int tiles = a.items / a.splits;
+  const int split = item / tiles;
+  int blk = item % tiles;
   int layer, tm, tn, cols;
   if (blk < a.tiles_l0) {
     layer = 0; cols = a.k1_half;
@@ -395,7 +407,14 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
     blk -= a.tiles_l0;
     layer = a.first_sq + blk / a.tiles_l; blk %= a.tiles_l;
     cols = a.width;
-    tm = blk / a.tn_l; tn = blk % a.tn_l;
+    if ((a.tn_l & 1) == 0 && ((a.tiles_l / a.tn_l) & 1) == 0) {
+      // 2 x 2 blocks of tiles, four consecutive tiles per block
+      const int q = blk >> 2, j = blk & 3, half_tn = a.tn_l >> 1;
+      tm = 2 * (q / half_tn) + (j >> 1);
+      tn = 2 * (q % half_tn) + (j & 1);
+    } else {
+      tm = blk / a.tn_l; tn = blk % a.tn_l;
+    }
   }
   const int W = a.width;
   const int row0 = tm * TM + (wave >> 1) * (TM / 2);
@@ -435,7 +454,7 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
   const bool do_bias = (tn == 0) && ((wave & 1) == 0);
 
   const int steps = (int)(a.R / KB) / a.splits;   // a multiple of 4
-  const int s0 = blockIdx.y * steps;
+  const int s0 = split * steps;
   Frag A[4][RTW], B[4][CTW];
   auto load = [&](int slot, int s) {
     const int sa = (s0 + s) * a_step, sb = (s0 + s) * b_step;
@@ -479,7 +498,7 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
   }
 
   const int fan_in = layer == 0 ? a.n_feat : W;
-  float* out = a.grad + (a.splits > 1 ? (int64_t)blockIdx.y * a.P : 0);
+  float* out = a.grad + (a.splits > 1 ? (int64_t)split * a.P : 0);
   float* gw = out + a.mo.w[layer];
 #pragma unroll
   for (int r = 0; r < RTW; ++r)
@@ -693,7 +712,9 @@ static hipError_t launch_dw(const ddf_net_desc& d, DwArgs& a, int lo0, int hi0, 
   a.first_sq = lo0 == 0 ? 1 : lo0;
   const int tiles = a.tiles_l0 + (hi0 - a.first_sq + 1) * a.tiles_l;
   if (tiles <= 0) return hipSuccess;
-  const dim3 grid((unsigned)tiles, (unsigned)a.splits);
+  a.items = tiles * a.splits;
+  const int groups = (a.items + 3) / 4;
+  const dim3 grid((unsigned)(32 * ((groups + 7) / 8)));
   if (T == 256)
     hipLaunchKernelGGL((dw_kernel<P, 256, 256>), grid, dim3(kThreads), 0, st, a);
   else
