@@ -7,7 +7,8 @@ features), random He-init weights (seed 0).  A timed step is one query of the
 whole batch (ray ingest, encoding, the fused layer chain and both heads) in
 the headline precision; the JSON line's `value` is the query throughput.
 Further legs run in the same invocation: the other query precisions on the same
-rays; distillation training steps (65,536 rays through the 12 x 1024 net, and
+rays (each reduced precision's |dt| and flip rate against the fp32 query); the
+bf16 and fp8 queries at 1K, 10K and 100K rays; distillation training steps (65,536 rays through the 12 x 1024 net, and
 262,144 rays through the 16 x 1024 net with activations recomputed every 4
 layers, bf16 and fp32 each); and sphere tracing of a signed-distance MLP of the
 same size along the same rays (the paper's baseline); and the paper's own 52 MB hash-grid
