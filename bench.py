@@ -234,7 +234,7 @@ def main():
     progress(f"queries done ({prec} {ms:.2f} ms/step)")
     if "sparse" in legs:
         # the sparse-query regime (the paper's 1K-100K ray counts): per-call time of the dense
-        # query in each reduced precision on the first n rays
+        # query in each reduced precision on the first n rays, and of the bf16 small-batch path
         sp = {}
         for p in ("bf16", "fp8"):
             pk = ddf.pack(desc, p, master, act_scales=scales if p == "fp8" else None)
@@ -249,6 +249,14 @@ def main():
                 torch.cuda.synchronize()
                 msn = timer.time(lambda: ddf.query_into(dc, pk, r, tq, xq), 20)
                 row[str(n)] = {"ms": msn, "rays_per_s": n / (msn * 1e-3), "us_per_ray": msn * 1e3 / n}
+                if p == "bf16":
+                    # the small-batch path: one launch per layer, neurons split over workgroups
+                    wsq = torch.empty(ddf.query_split_workspace_bytes(desc, n), dtype=torch.uint8, device=dev)
+                    for _ in range(3):
+                        ddf.query_split(desc, pk, r, ws=wsq, t=tq, xi=xq)
+                    torch.cuda.synchronize()
+                    msn = timer.time(lambda: ddf.query_split(desc, pk, r, ws=wsq, t=tq, xi=xq), 20)
+                    row[str(n)]["split"] = {"ms": msn, "rays_per_s": n / (msn * 1e-3), "us_per_ray": msn * 1e3 / n}
             sp[p] = row
         out["sparse_queries"] = sp
         progress("sparse leg done")

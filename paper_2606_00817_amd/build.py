@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libddf.so")
-SOURCES = ["ddf_api.hip", "ddf_pack.hip", "ddf_fwd.hip", "ddf_fwd8.hip", "ddf_train.hip", "ddf_hash.hip", "ddf_shade.hip"]
+SOURCES = ["ddf_api.hip", "ddf_pack.hip", "ddf_fwd.hip", "ddf_fwd8.hip", "ddf_train.hip", "ddf_hash.hip", "ddf_shade.hip", "ddf_split.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed-fp32 instructions in any generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -60,6 +60,8 @@ SIGNATURES = {
     "ddf_packed_bytes": (_SZ, [_D]),
     "ddf_pack": (ctypes.c_int, [_D, _P, ctypes.POINTER(ctypes.c_float), _P, _P]),
     "ddf_query": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, _P]),
+    "ddf_query_split_workspace_bytes": (_SZ, [_D, _I64]),
+    "ddf_query_split": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, _P, _SZ, _P]),
     "ddf_fp8_calib_workspace_bytes": (_SZ, [_D, _I64]),
     "ddf_fp8_act_scales": (ctypes.c_int, [_D, _P, _P, _I64, ctypes.POINTER(ctypes.c_float), _P, _SZ, _P]),
     "ddf_train_workspace_bytes": (_SZ, [_D, _I64, ctypes.c_int32]),
@@ -183,6 +185,24 @@ def query_into(desc_ct: NetDescC, packed, rays, t, xi, stream=None):
     """Allocation-free query on prepared tensors (benchmark loop)."""
     _check(lib().ddf_query(ctypes.byref(desc_ct), _ptr(packed), _ptr(rays), rays.shape[1], _ptr(t), _ptr(xi),
                            stream if stream is not None else _stream()))
+
+
+def query_split_workspace_bytes(desc, n) -> int:
+    return int(lib().ddf_query_split_workspace_bytes(ctypes.byref(desc_c(desc, "bf16")), int(n)))
+
+
+def query_split(desc, packed, rays, ws=None, t=None, xi=None):
+    """The small-batch bf16 query (one launch per layer, neurons split over workgroups)."""
+    _dev(rays, torch.float32, "rays")
+    d = desc_c(desc, "bf16")
+    n = rays.shape[1]
+    t = torch.empty(n, dtype=torch.float32, device=rays.device) if t is None else t
+    xi = torch.empty(n, dtype=torch.float32, device=rays.device) if xi is None else xi
+    if ws is None:
+        ws = torch.empty(max(256, query_split_workspace_bytes(desc, n)), dtype=torch.uint8, device=rays.device)
+    _check(lib().ddf_query_split(ctypes.byref(d), _ptr(packed), _ptr(rays), n, _ptr(t), _ptr(xi), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream()))
+    return t, xi
 
 
 def sdf_eval(desc, precision, packed, points):
