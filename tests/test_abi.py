@@ -104,3 +104,20 @@ def test_hash_layout_matches_oracle():
     with pytest.raises(ddf.DDFError):
         ddf.hash_param_count(bad)
     assert ddf.hash_query_workspace_bytes(bad, 1000) == 0
+
+
+def test_workspace_sizing_calls():
+    """Host-side sizing: the small-batch query keeps two [R][width] bf16 activation buffers
+    (R = n rounded up to 64) and [width / 128][R][2] float head partials, each 256-byte
+    aligned; the float16 hash table is 2 halves per entry; unsupported shapes size to 0."""
+    from oracle import hashgrid_oracle as H
+    a256 = lambda x: (x + 255) // 256 * 256
+    for n in (1, 1000, 4097):
+        R = (n + 63) // 64 * 64
+        want = 2 * a256(R * 1024 * 2) + a256(8 * R * 2 * 4)
+        assert ddf.query_split_workspace_bytes(I.NET_FULL, n) == want
+    assert ddf.query_split_workspace_bytes(I.NET_TINY, 100) == 0     # width 128: not built
+    import ctypes
+    for d in (I.HASH_PAPER, I.HASH_SMALL):
+        c = ddf.hash_desc_c(d)
+        assert ddf.lib().ddf_hash_table_f16_bytes(ctypes.byref(c)) == H.table_entries(d) * 2 * 2
