@@ -735,13 +735,16 @@ __global__ __launch_bounds__(kHT) void dense_bwd_kernel(const float* d_out, cons
 }
 
 // The position-code gradient dg [R][64] (first 2 NL entries) of every live ray scattered to
-// the 8 corners of every level with the lookup weights (float atomics).
+// the 8 corners of every level with the lookup weights (float atomics).  Like the lookups,
+// the work goes out as 8 x (ray blocks) workgroups, workgroup index g (mod 8) taking level
+// group g: all updates of a group's table entries then come from one XCD.
 template <int NL>
 __global__ __launch_bounds__(kHT) void hash_scatter_kernel(HashArgs a, const float* dg) {
   __shared__ LevelTab lt;
   stage_levels(a.L, lt);
   __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int g = blockIdx.x % kHGroups;
+  const int64_t r = (int64_t)(blockIdx.x / kHGroups) * blockDim.x + threadIdx.x;
   if (r >= a.n) return;
   float x[3];
 #pragma unroll
@@ -749,7 +752,9 @@ __global__ __launch_bounds__(kHT) void hash_scatter_kernel(HashArgs a, const flo
   float p[3];
   unit_point(lt, x, p);
 #pragma unroll
-  for (int l = 0; l < NL; ++l) {
+  for (int slot = 0; slot < 2; ++slot) {
+    const int l = grp_level<NL>(g, slot);
+    if (l < 0) continue;
     const float2 gl = *reinterpret_cast<const float2*>(dg + r * kHIn + 2 * l);
     uint32_t c[3];
     float w[3];
@@ -886,7 +891,7 @@ int run_hash_encode(const HashArgs& a, hipStream_t st) {
 }
 
 int run_hash_scatter(const HashArgs& a, const float* dg, hipStream_t st) {
-  const unsigned blocks = (unsigned)((a.n + kHT - 1) / kHT);
+  const unsigned blocks = (unsigned)((a.n + kHT - 1) / kHT) * kHGroups;
   if (a.L.n_levels == 16)
     hash_scatter_kernel<16><<<blocks, kHT, 0, st>>>(a, dg);
   else
