@@ -35,3 +35,17 @@ def test_sample_rays_match_oracle(mode, n, tries):
     assert np.isfinite(r).all() and (np.abs(r[:, 0:3]) <= 1.5 + 1e-3 + 1e-5).all()
     print(f"sampler mode {mode} n={n} tries={tries}: clear {clear.mean():.4f}, "
           f"max |do| {np.abs(r[clear, 0:3] - ref[clear, 0:3]).max() if clear.any() else 0:.2e}")
+
+
+def test_sample_rays_argument_errors():
+    dev = cuda()
+    prims = _t(ddf.scene_prims(I.scene_ground(4, 5)), dev)
+    u = torch.rand((3 * 4 + 2, 64), device=dev)
+    with pytest.raises(ddf.DDFError, match="mode"):
+        ddf.sample_rays(prims, u, mode=3)
+    with pytest.raises(ddf.DDFError, match="rows"):
+        ddf.sample_rays(prims, u, tries=5)        # 17 rows needed
+    with pytest.raises(ddf.DDFError, match="box_half"):
+        ddf.sample_rays(prims, u, box_half=0.0)
+    with pytest.raises(ddf.DDFError, match="tries"):
+        ddf.sample_rays(prims, torch.rand((3 * 17 + 2, 64), device=dev), tries=17)
