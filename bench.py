@@ -522,7 +522,7 @@ def fit_sdf(torch, ddf, I, dev, scene, steps=400, batch=65536, prec="bf16", seed
     held_gt = ddf.scene_sdf(prims, held)
     packed32 = ddf.pack(desc, "fp32", master)
     err = (ddf.sdf_eval(desc, "fp32", packed32, held) - held_gt).abs()
-    return packed32, {"steps": steps, "batch": batch, "precision": prec, "final_loss": float(loss[0].item()),
+    return (packed32, ddf.pack(desc, "bf16", master)), {"steps": steps, "batch": batch, "precision": prec, "final_loss": float(loss[0].item()),
                       "heldout_mean_abs_err": float(err.mean().item()),
                       "heldout_p90_abs_err": float(err.quantile(0.9).item())}
 
@@ -531,9 +531,10 @@ def trace_leg(torch, ddf, I, dev, rays, timer, out, scene):
     """Sphere tracing of a 12 x 1024 signed-distance MLP along the same shadow rays.
 
     The SDF MLP is fitted to the scene first (fit_sdf); the trace runs in fp32 with at most
-    128 steps, hit at |s| < 1e-4, miss beyond t = 6."""
+    128 steps, hit at |s| < 1e-4, miss beyond t = 6; then once more in bf16 with the same
+    settings (the same-precision comparison with the bf16 DDF query)."""
     desc = I.NET_SDF
-    packed, fit = fit_sdf(torch, ddf, I, dev, scene)
+    (packed, packed_bf16), fit = fit_sdf(torch, ddf, I, dev, scene)
     n = rays.shape[1]
     ws = torch.empty(int(ddf.lib().sdf_trace_workspace_bytes(n)), dtype=torch.uint8, device=dev)
     ddf.sphere_trace(desc, "fp32", packed, rays, 128, 1e-4, 6.0, ws=ws)
@@ -555,6 +556,16 @@ def trace_leg(torch, ddf, I, dev, rays, timer, out, scene):
         msp = prec.get(p, {}).get("ms") if p != out["dtype"] else out["ms_per_step"]
         if msp:
             res[f"speedup_vs_ddf_{p}"] = ms / msp
+    # the bf16 trace (one timed run)
+    ms16 = timer.time(lambda: ddf.sphere_trace(desc, "bf16", packed_bf16, rays, 128, 1e-4, 6.0, ws=ws), 1)
+    t16, hit16, steps16 = ddf.sphere_trace(desc, "bf16", packed_bf16, rays, 128, 1e-4, 6.0, ws=ws)
+    s16 = steps16.float()
+    res["bf16"] = {"ms": ms16, "rays_per_s": n / (ms16 * 1e-3), "mean_steps": float(s16.mean().item()),
+                   "unconverged_fraction": float((steps16 >= 128).float().mean().item()),
+                   "hit_agreement_vs_exact_cast": float((hit16 == hg).float().mean().item())}
+    msb = prec.get("bf16", {}).get("ms") if out["dtype"] != "bf16" else out["ms_per_step"]
+    if msb:
+        res["bf16"]["speedup_vs_ddf_bf16"] = ms16 / msb
     return res
 
 

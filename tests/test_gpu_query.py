@@ -145,6 +145,34 @@ def test_sphere_trace_planted_box_matches_oracle():
     assert np.all(np.abs(box_sdf(p, half)) < 2e-4)
 
 
+def test_sphere_trace_bf16_planted_box():
+    """The bf16 trace (the same-precision baseline of the bf16 query): the same rays and
+    settings as the fp32 trace, hit decisions agree with the float64 trace on most rays and
+    every bf16 hit lies near the planted box surface (bf16 rounds the SDF to ~3 digits)."""
+    dev = cuda()
+    desc = I.NetDesc(3, 10, 6, 256, 1)
+    half = [0.3, 0.5, 0.7]
+    params = planted_box_sdf(desc, half, 7)
+    rng = np.random.default_rng(3)
+    o = rng.uniform(-1.5, 1.5, (64 * 9 + 3, 3))
+    o = o[np.max(np.abs(o) - half, axis=1) > 0.05][: 64 * 5 + 3]
+    aim = rng.uniform(-0.2, 0.2, (len(o), 3))
+    d = np.where(rng.uniform(size=(len(o), 1)) < 0.7, aim - o, rng.standard_normal((len(o), 3)))
+    rays = I._soa(o, d)
+    packed = ddf.pack(desc, "bf16", _t(params, dev))
+    t, hit, steps = ddf.sphere_trace(desc, "bf16", packed, _t(rays, dev), max_steps=128, hit_eps=1e-4, t_max=6.0)
+    torch.cuda.synchronize()
+    t = t.cpu().numpy(); hit = hit.cpu().numpy().astype(bool); steps = steps.cpu().numpy()
+    ro = rays[0:3].T.astype(np.float64); rd = rays[3:6].T.astype(np.float64)
+    tr, hr, sr, done = G.sphere_trace(lambda p: O.sdf_eval(desc, params, p), ro, rd, 128, 1e-4, 6.0)
+    print(f"bf16 trace: {hit.mean():.2f} hit (fp64 {hr.mean():.2f}), steps mean {steps.mean():.1f}, "
+          f"hit agreement {(hit == hr).mean():.4f}")
+    assert np.isfinite(t).all() and (steps >= 1).all() and (steps <= 128).all()
+    assert (hit == hr).mean() > 0.9
+    p = ro[hit] + t[hit, None] * rd[hit]
+    assert np.all(np.abs(box_sdf(p, half)) < 2e-2)
+
+
 def _calib_rays():
     return I.free_rays(I.scene_mixed(256, 2), 4096, 21)
 
