@@ -142,6 +142,8 @@ def main():
                          "cpu, copy")
     ap.add_argument("--shade-steps", type=int, default=30000,
                     help="recipe steps of the hash-grid field trained for the shade leg")
+    ap.add_argument("--sdf-fit-steps", type=int, default=400,
+                    help="fitting steps of the SDF MLP the trace leg sphere-traces")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
@@ -270,7 +272,7 @@ def main():
         progress("train_large leg done")
 
     if "trace" in legs:
-        out["sphere_trace"] = trace_leg(torch, ddf, I, dev, rays, timer, out, scene)
+        out["sphere_trace"] = trace_leg(torch, ddf, I, dev, rays, timer, out, scene, args.sdf_fit_steps)
         progress("trace leg done")
 
     if "hash" in legs:
@@ -527,14 +529,14 @@ def fit_sdf(torch, ddf, I, dev, scene, steps=400, batch=65536, prec="bf16", seed
                       "heldout_p90_abs_err": float(err.quantile(0.9).item())}
 
 
-def trace_leg(torch, ddf, I, dev, rays, timer, out, scene):
+def trace_leg(torch, ddf, I, dev, rays, timer, out, scene, fit_steps=400):
     """Sphere tracing of a 12 x 1024 signed-distance MLP along the same shadow rays.
 
     The SDF MLP is fitted to the scene first (fit_sdf); the trace runs in fp32 with at most
     128 steps, hit at |s| < 1e-4, miss beyond t = 6; then once more in bf16 with the same
     settings (the same-precision comparison with the bf16 DDF query)."""
     desc = I.NET_SDF
-    (packed, packed_bf16), fit = fit_sdf(torch, ddf, I, dev, scene)
+    (packed, packed_bf16), fit = fit_sdf(torch, ddf, I, dev, scene, steps=fit_steps)
     n = rays.shape[1]
     ws = torch.empty(int(ddf.lib().sdf_trace_workspace_bytes(n)), dtype=torch.uint8, device=dev)
     ddf.sphere_trace(desc, "fp32", packed, rays, 128, 1e-4, 6.0, ws=ws)
