@@ -120,10 +120,14 @@ def cpu_oracle_baseline(desc, params, rays_np, answers, budget_s=12.0):
 
 
 def dt_stats(t_ref, x_ref, t, xi):
-    """max/mean |dt| and visibility flip rate (xi > 0.5) of answers against reference answers."""
+    """max/mean |dt| and visibility flip rate (xi > 0.5) of answers against reference answers,
+    and the share of reference answers within |z_xi| < 1e-3 of the decision (|xi - 0.5| <
+    2.5e-4), where a flip costs nothing."""
     d = np.abs(np.asarray(t, dtype=np.float64) - np.asarray(t_ref, dtype=np.float64))
+    xr = np.asarray(x_ref, dtype=np.float64)
     return {"max_abs_dt": float(d.max()), "mean_abs_dt": float(d.mean()),
-            "flip_rate": float(((np.asarray(xi) > 0.5) != (np.asarray(x_ref) > 0.5)).mean()), "rays": int(d.size)}
+            "flip_rate": float(((np.asarray(xi) > 0.5) != (xr > 0.5)).mean()),
+            "near_threshold_fraction": float((np.abs(xr - 0.5) < 2.5e-4).mean()), "rays": int(d.size)}
 
 
 def progress(msg):
@@ -260,6 +264,18 @@ def main():
                     msn = timer.time(lambda: ddf.query_split(desc, pk, r, ws=wsq, t=tq, xi=xq), 20)
                     row[str(n)]["split"] = {"ms": msn, "rays_per_s": n / (msn * 1e-3), "us_per_ray": msn * 1e3 / n}
             sp[p] = row
+        # the tiny configuration: 4,096 free rays through the 4 x 128 net in fp32 (launch-bound)
+        dt_ = I.NET_TINY
+        pk = ddf.pack(dt_, "fp32", torch.from_numpy(I.he_init(dt_, 0)).to(dev))
+        rt_ = torch.from_numpy(I.free_rays(I.scene_spheres(16, 1), 4096, 11)).to(dev)
+        tq = torch.empty(4096, dtype=torch.float32, device=dev)
+        xq = torch.empty(4096, dtype=torch.float32, device=dev)
+        dct = ddf.desc_c(dt_, "fp32")
+        for _ in range(3):
+            ddf.query_into(dct, pk, rt_, tq, xq)
+        torch.cuda.synchronize()
+        mst = timer.time(lambda: ddf.query_into(dct, pk, rt_, tq, xq), 50)
+        sp["tiny_4x128_fp32_4096_rays"] = {"us_per_launch": mst * 1e3, "rays_per_s": 4096 / (mst * 1e-3)}
         out["sparse_queries"] = sp
         progress("sparse leg done")
     if "train" in legs:
@@ -547,7 +563,11 @@ def trace_leg(torch, ddf, I, dev, rays, timer, out, scene, fit_steps=400):
     tg, hg = ddf.cast_targets(prims, rays)
     st = steps.float()
     prec = out.get("precisions", {})
+    hist = torch.bincount(steps.long().clamp(0, 128), minlength=129).cpu().numpy()
+    edges = [1, 2, 4, 8, 16, 32, 64, 128, 129]
     res = {"sdf": "12x1024 SDF MLP (L=10, 63 features) fitted to the scene's distance bound",
+           "steps_histogram": {f"{edges[i]}-{edges[i + 1] - 1}": int(hist[edges[i]:edges[i + 1]].sum())
+                               for i in range(len(edges) - 1)},
            "fit": fit, "precision": "fp32", "max_steps": 128, "hit_eps": 1e-4, "t_max": 6.0,
            "ms": ms, "rays_per_s": n / (ms * 1e-3), "mean_steps": float(st.mean().item()),
            "p50_steps": float(st.median().item()), "max_steps_used": int(steps.max().item()),
