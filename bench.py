@@ -44,8 +44,8 @@ COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 TRAFFIC_KIB = {
     "bf16": {"FETCH_SIZE": 5925033, "WRITE_SIZE": 8192,
              "sha256": "439fb400e43d5295381397c33c0c19e59a467b2b043bf0249a40ecff96a16f51"},
-    "fp8": {"FETCH_SIZE": 1552400, "WRITE_SIZE": 61710,
-            "sha256": "acb00b46490c40646f485a71af6860aefd2eedaaadbc56b6b8c75b365315fb92"},
+    "fp8": {"FETCH_SIZE": 1552400, "WRITE_SIZE": 61420,
+            "sha256": "7ff934cdecf1833492721fd4307502ddf9399290488ff3a8c1836dfd30e63c36"},
 }
 KERNEL_SOURCES = {
     "fp32": ["ddf_fwd.hip", "ddf_chain.h", "ddf_fwd.h", "ddf_internal.h"],

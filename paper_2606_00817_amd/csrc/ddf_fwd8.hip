@@ -53,6 +53,18 @@ __device__ inline uint32_t pack_e4m3(float y0, float y1, float y2, float y3) {
   return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y2, y3, lo, true);
 }
 
+// The four e4m3 words of one ray and one 32-neuron tile, lane el holding neurons
+// 8 q + 4 (el / 32) + i of it in word q, regrouped by two lane-half swaps so that lanes below
+// 32 hold neurons 0 .. 15 and the others 16 .. 31, as 16 contiguous bytes each.  One 128-bit
+// LDS write per tile then replaces four 32-bit writes: at the row stride of WIDTH + 16 bytes
+// the 32 rows of a 32-bit write fall into only 8 banks, while the 128-bit write (like the
+// products' 128-bit reads) spreads its rows over all of them.
+__device__ inline i32x4 regroup16(const uint32_t (&w)[4]) {
+  const auto s02 = __builtin_amdgcn_permlane32_swap(w[0], w[2], false, false);
+  const auto s13 = __builtin_amdgcn_permlane32_swap(w[1], w[3], false, false);
+  return i32x4{(int)s02[0], (int)s02[1], (int)s13[0], (int)s13[1]};
+}
+
 // acc[rt][t] += G[rt rows][0:K1] * W1[tile (tile0 + t)][0:K1]^T   (bf16 operands, 1 KiB
 // blocks).  The weight loads run two blocks ahead in a ring of three; the loads past the end
 // of the layer are bounds-checked by the buffer resource (zeros, never used).
@@ -246,8 +258,11 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
     const float* bias = bsm;
     // Operand roles are swapped (weights as the first matrix-core operand): register group q
     // of tile (rt, t) holds neurons (tile0 + t) 32 + 8 q + 4 (lane / 32) + i, i < 4, of ray
-    // rt 32 + lane % 32, so 4 consecutive e4m3 results leave as one 32-bit LDS write.
-    uint32_t hold[kRT8][NTP][4];             // pass-0 e4m3 results, 4 neurons per word
+    // rt 32 + lane % 32: 4 consecutive e4m3 results form one word, and regroup16 turns a
+    // tile's four words into one 128-bit LDS write.
+    // pass-0 e4m3 results, regrouped; kept as separate words, since aligned 4-register
+    // tuples live across the second pass make the 1024-wide kernel spill ten times more
+    uint32_t hold[kRT8][NTP][4];
     float hp0[kRT8], hp1[kRT8];
 #pragma unroll
     for (int rt = 0; rt < kRT8; ++rt) { hp0[rt] = 0.f; hp1[rt] = 0.f; }
@@ -310,16 +325,14 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
 #pragma unroll
           for (int rt = 0; rt < kRT8; ++rt)
 #pragma unroll
-            for (int t = 0; t < NTP; ++t) {
-              const int nb = (wave * NTW + t) * 32 + 4 * (el >> 5);
-#pragma unroll
-              for (int q = 0; q < 4; ++q)
-                *reinterpret_cast<uint32_t*>(X + (rt * 32 + (el & 31)) * LDX + nb + 8 * q) = hold[rt][t][q];
-            }
+            for (int t = 0; t < NTP; ++t)
+              *reinterpret_cast<i32x4*>(X + (rt * 32 + (el & 31)) * LDX + (wave * NTW + t) * 32 + 16 * (el >> 5)) =
+                  i32x4{(int)hold[rt][t][0], (int)hold[rt][t][1], (int)hold[rt][t][2], (int)hold[rt][t][3]};
         }
 #pragma unroll
         for (int t = 0; t < NTP; ++t) {
           const int nb = (tile0 + t) * 32 + 4 * (el >> 5);
+          uint32_t w[kRT8][4];
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             // relu(acc dq + b) / s_A,next in one rounding: the scales are powers of two, so
@@ -334,12 +347,17 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
 #pragma unroll
               for (int i = 0; i < 4; ++i)   // ReLU and saturation at 448 in one clamp
                 y[i] = __builtin_amdgcn_fmed3f(fmaf(acc[rt][t][4 * q + i], dqn, bq[i]), 0.f, 448.f);
-              const uint32_t w = pack_e4m3(y[0], y[1], y[2], y[3]);
-              if (p == 0)
-                hold[rt][t][q] = w;
-              else
-                *reinterpret_cast<uint32_t*>(X + (rt * 32 + (el & 31)) * LDX + nb + 8 * q) = w;
+              w[rt][q] = pack_e4m3(y[0], y[1], y[2], y[3]);
             }
+          }
+#pragma unroll
+          for (int rt = 0; rt < kRT8; ++rt) {
+            const i32x4 v = regroup16(w[rt]);
+            if (p == 0) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) hold[rt][t][q] = (uint32_t)v[q];
+            } else
+              *reinterpret_cast<i32x4*>(X + (rt * 32 + (el & 31)) * LDX + (tile0 + t) * 32 + 16 * (el >> 5)) = v;
           }
           __builtin_amdgcn_sched_barrier(0);
         }
