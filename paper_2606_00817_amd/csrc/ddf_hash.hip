@@ -737,35 +737,44 @@ __global__ __launch_bounds__(kHT) void dense_bwd_kernel(const float* d_out, cons
 // The position-code gradient dg [R][64] (first 2 NL entries) of every live ray scattered to
 // the 8 corners of every level with the lookup weights (float atomics).  Like the lookups,
 // the work goes out as 8 x (ray blocks) workgroups, workgroup index g (mod 8) taking level
-// group g: all updates of a group's table entries then come from one XCD.
+// group g: all updates of a group's table entries then come from one XCD.  Four lanes share
+// a ray, lane s of the four taking the corners at x offset s / 2 and feature s % 2: in each
+// atomic instruction the lanes of a ray address the two features of the two x-neighbour
+// corners, 16 contiguous bytes on the dense levels and on hashed levels when the lower
+// corner's x is even (x enters the hash with multiplier 1), so the updates of one ray leave
+// as one request per line instead of four.
+constexpr int kHSub = 4;                  // lanes per ray in the scatter
 template <int NL>
 __global__ __launch_bounds__(kHT) void hash_scatter_kernel(HashArgs a, const float* dg) {
   __shared__ LevelTab lt;
   stage_levels(a.L, lt);
   __syncthreads();
   const int g = blockIdx.x % kHGroups;
-  const int64_t r = (int64_t)(blockIdx.x / kHGroups) * blockDim.x + threadIdx.x;
+  const int sub = threadIdx.x % kHSub;
+  const int64_t r = (int64_t)(blockIdx.x / kHGroups) * (kHT / kHSub) + threadIdx.x / kHSub;
   if (r >= a.n) return;
   float x[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) x[c] = a.rays[c * a.n + r];
   float p[3];
   unit_point(lt, x, p);
+  // the lane's feature, and the low corner bits it owns (the rest run in the loop)
+  const int f = sub & 1, klo = sub >> 1;
+  constexpr int kLoBits = kHSub == 2 ? 0 : (kHSub == 4 ? 1 : 2);
 #pragma unroll
   for (int slot = 0; slot < 2; ++slot) {
     const int l = grp_level<NL>(g, slot);
     if (l < 0) continue;
-    const float2 gl = *reinterpret_cast<const float2*>(dg + r * kHIn + 2 * l);
+    const float gl = dg[r * kHIn + 2 * l + f];
     uint32_t c[3];
     float w[3];
     cell((float)lt.res[l], p, c, w);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int j = 0; j < (8 >> kLoBits); ++j) {
       int64_t e;
       float wt;
-      corner(lt, l, c, w, k, e, wt);
-      atomicAdd(a.gtab + 2 * e, wt * gl.x);
-      atomicAdd(a.gtab + 2 * e + 1, wt * gl.y);
+      corner(lt, l, c, w, klo | (j << kLoBits), e, wt);
+      atomicAdd(a.gtab + 2 * e + f, wt * gl);
     }
   }
 }
@@ -891,7 +900,8 @@ int run_hash_encode(const HashArgs& a, hipStream_t st) {
 }
 
 int run_hash_scatter(const HashArgs& a, const float* dg, hipStream_t st) {
-  const unsigned blocks = (unsigned)((a.n + kHT - 1) / kHT) * kHGroups;
+  constexpr int rays_per_block = kHT / kHSub;
+  const unsigned blocks = (unsigned)((a.n + rays_per_block - 1) / rays_per_block) * kHGroups;
   if (a.L.n_levels == 16)
     hash_scatter_kernel<16><<<blocks, kHT, 0, st>>>(a, dg);
   else

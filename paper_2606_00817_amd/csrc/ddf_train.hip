@@ -127,6 +127,32 @@ __device__ inline void kahan_add(float& s, float& c, float x) {
   s = t;
 }
 
+// Fixed-order reduction of the block's kThreads rows of red: row t absorbs row t + stride for
+// stride = kThreads / 2 .. 1.  Column pairs (2j, 2j + 1), j < NP, are (sum, compensation) and
+// merge as a compensated sum; the other columns add plainly.  Row 0 ends with the block's
+// total.  Called by all kThreads threads of the block, after each has written its row.
+template <int NC, int NP>
+__device__ inline void tree_sum(float (*red)[NC]) {
+  const int t = threadIdx.x;
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    __syncthreads();
+    if (t < st) {
+#pragma unroll
+      for (int j = 0; j < NP; ++j) {
+        float sj = red[t][2 * j], cj = red[t][2 * j + 1];
+        kahan_add(sj, cj, red[t + st][2 * j]);
+        red[t][2 * j] = sj;
+        red[t][2 * j + 1] = cj + red[t + st][2 * j + 1];
+      }
+#pragma unroll
+      for (int j = 2 * NP; j < NC; ++j) red[t][j] += red[t + st][j];
+    }
+  }
+  __syncthreads();
+}
+
+static_assert(kLossBlocks == kThreads, "the final loss reduction gives each block partial a thread");
+
 struct LossArgs {
   const float* zt; const float* zx; const float* tgt; const uint8_t* hit;
   int64_t n, R;
@@ -154,28 +180,23 @@ __global__ void loss_partial_kernel(LossArgs a) {
   __shared__ float red[kThreads][5];
   red[threadIdx.x][0] = l1; red[threadIdx.x][1] = l1c;
   red[threadIdx.x][2] = bce; red[threadIdx.x][3] = bcec; red[threadIdx.x][4] = hits;
-  __syncthreads();
+  tree_sum<5, 2>(red);
   if (threadIdx.x == 0) {
-    float s0 = 0.f, c0 = 0.f, s1 = 0.f, c1 = 0.f, h = 0.f;
-    for (int t = 0; t < kThreads; ++t) {      // fixed order
-      kahan_add(s0, c0, red[t][0]); c0 += red[t][1];
-      kahan_add(s1, c1, red[t][2]); c1 += red[t][3];
-      h += red[t][4];
-    }
     float* p = a.partial + blockIdx.x * 8;
-    p[0] = s0; p[1] = c0; p[2] = s1; p[3] = c1; p[4] = h;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) p[j] = red[0][j];
   }
 }
 
+// One block of kThreads threads, one per block partial.
 __global__ void loss_final_kernel(LossArgs a) {
+  __shared__ float red[kThreads][5];
+  const float* p = a.partial + threadIdx.x * 8;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) red[threadIdx.x][j] = p[j];
+  tree_sum<5, 2>(red);
   if (threadIdx.x != 0) return;
-  float s0 = 0.f, c0 = 0.f, s1 = 0.f, c1 = 0.f, h = 0.f;
-  for (int b = 0; b < kLossBlocks; ++b) {
-    const float* p = a.partial + b * 8;
-    kahan_add(s0, c0, p[0]); c0 += p[1];
-    kahan_add(s1, c1, p[2]); c1 += p[3];
-    h += p[4];
-  }
+  const float s0 = red[0][0], c0 = red[0][1], s1 = red[0][2], c1 = red[0][3], h = red[0][4];
   const float l1 = h > 0.f ? (s0 + c0) / h : 0.f;
   const float bce = a.n > 0 ? (s1 + c1) / (float)a.n : 0.f;
   a.scal[0] = h > 0.f ? 1.f / h : 0.f;
@@ -215,19 +236,21 @@ __global__ void sdf_loss_partial_kernel(LossArgs a) {
     kahan_add(l1, l1c, fabsf(a.zt[i] - a.tgt[i]));
   __shared__ float red[kThreads][2];
   red[threadIdx.x][0] = l1; red[threadIdx.x][1] = l1c;
-  __syncthreads();
+  tree_sum<2, 1>(red);
   if (threadIdx.x == 0) {
-    float s0 = 0.f, c0 = 0.f;
-    for (int t = 0; t < kThreads; ++t) { kahan_add(s0, c0, red[t][0]); c0 += red[t][1]; }
     float* p = a.partial + blockIdx.x * 8;
-    p[0] = s0; p[1] = c0; p[2] = 0.f; p[3] = 0.f; p[4] = 0.f;
+    p[0] = red[0][0]; p[1] = red[0][1]; p[2] = 0.f; p[3] = 0.f; p[4] = 0.f;
   }
 }
 
+// One block of kThreads threads, one per block partial.
 __global__ void sdf_loss_final_kernel(LossArgs a) {
+  __shared__ float red[kThreads][2];
+  red[threadIdx.x][0] = a.partial[threadIdx.x * 8];
+  red[threadIdx.x][1] = a.partial[threadIdx.x * 8 + 1];
+  tree_sum<2, 1>(red);
   if (threadIdx.x != 0) return;
-  float s0 = 0.f, c0 = 0.f;
-  for (int b = 0; b < kLossBlocks; ++b) { kahan_add(s0, c0, a.partial[b * 8]); c0 += a.partial[b * 8 + 1]; }
+  const float s0 = red[0][0], c0 = red[0][1];
   const float l = a.n > 0 ? (s0 + c0) / (float)a.n : 0.f;
   a.loss_out[0] = l; a.loss_out[1] = l; a.loss_out[2] = 0.f;
 }
@@ -827,7 +850,7 @@ int launch_ddf_loss(const float* zt, const float* zx, const float* t_gt, const u
   la.partial = partial; la.scal = scal; la.loss_out = loss_out; la.dzt = dzt; la.dzx = dzx;
   la.bce_weight = bce_weight; la.clamp = clamp;
   loss_partial_kernel<<<kLossBlocks, kThreads, 0, st>>>(la);
-  loss_final_kernel<<<1, 64, 0, st>>>(la);
+  loss_final_kernel<<<1, kThreads, 0, st>>>(la);
   loss_grad_kernel<<<(unsigned)((R + 255) / 256), 256, 0, st>>>(la);
   return hip_status(hipGetLastError(), "loss launch");
 }
@@ -938,7 +961,7 @@ int ddf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
   la.dzx = reinterpret_cast<float*>(wb + w.dzx);
   la.bce_weight = hp->bce_weight; la.clamp = hp->l1_clamp;
   loss_partial_kernel<<<kLossBlocks, kThreads, 0, st>>>(la);
-  loss_final_kernel<<<1, 64, 0, st>>>(la);
+  loss_final_kernel<<<1, kThreads, 0, st>>>(la);
   loss_grad_kernel<<<(unsigned)((w.R + 255) / 256), 256, 0, st>>>(la);
   if ((rc = hip_status(hipGetLastError(), "loss launch"))) return rc;
   float* grad = grad_out ? grad_out : reinterpret_cast<float*>(wb + w.grad);
@@ -977,7 +1000,7 @@ int sdf_train_step(const ddf_net_desc* d, float* master, float* adam_m, float* a
   la.dzt = reinterpret_cast<float*>(wb + w.dzt);
   la.dzx = reinterpret_cast<float*>(wb + w.dzx);
   sdf_loss_partial_kernel<<<kLossBlocks, kThreads, 0, st>>>(la);
-  sdf_loss_final_kernel<<<1, 64, 0, st>>>(la);
+  sdf_loss_final_kernel<<<1, kThreads, 0, st>>>(la);
   sdf_loss_grad_kernel<<<(unsigned)((w.R + 255) / 256), 256, 0, st>>>(la);
   if ((rc = hip_status(hipGetLastError(), "sdf loss launch"))) return rc;
   float* grad = grad_out ? grad_out : reinterpret_cast<float*>(wb + w.grad);
