@@ -598,12 +598,6 @@ __global__ __launch_bounds__(kHT) void hash_mlp_kernel(HashArgs a, const float* 
   }
 }
 
-__device__ inline void store_row(float* dst, const float (&v)[kHW]) {
-  f32x4* d4 = reinterpret_cast<f32x4*>(dst);
-#pragma unroll
-  for (int q = 0; q < kHW / 4; ++q) d4[q] = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
-}
-
 // ---- training: one simple kernel per stage, activations in memory ([R][64] per layer)
 
 // The input code of every ray (rows n .. R - 1: the code of the box centre, zero direction).
@@ -660,34 +654,81 @@ __global__ __launch_bounds__(kHT) void hash_encode_kernel(HashArgs a) {
   for (int q = 0; q < kHIn / 4; ++q) dst[q] = f32x4{g[4 * q], g[4 * q + 1], g[4 * q + 2], g[4 * q + 3]};
 }
 
+// h[j] += row[j] v, j < N (row: N consecutive weights in LDS, 16-byte aligned when N % 4 == 0).
+template <int N>
+__device__ __forceinline__ void axpy_n(const float* row, float v, float (&h)[N]) {
+  if constexpr (N % 4 == 0) {
+    const f32x4* r4 = reinterpret_cast<const f32x4*>(row);
+#pragma unroll
+    for (int q = 0; q < N / 4; ++q) {
+      const f32x4 w4 = r4[q];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) h[4 * q + e] = fmaf(w4[e], v, h[4 * q + e]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < N; ++j) h[j] = fmaf(row[j], v, h[j]);
+  }
+}
+
+// The [64][64] LDS image of a layer's weights, element (u, v) = W[row(u, v)][col(u, v)] or 0
+// outside [O][fan_in]; every thread's 16 loads are issued before its LDS writes.
+template <bool kTransposed>
+__device__ __forceinline__ void stage_weights(const float* W, int O, int fan_in, float (*dst)[kHW]) {
+  static_assert(kHIn == kHW && (kHIn * kHW) % kHT == 0, "square 64 x 64 image, whole rounds");
+  constexpr int kRounds = kHIn * kHW / kHT;
+  float v[kRounds];
+#pragma unroll
+  for (int it = 0; it < kRounds; ++it) {
+    const int k = it * kHT + (int)threadIdx.x;
+    const int u = k / kHW, c = k % kHW;
+    const int o = kTransposed ? c : u, i = kTransposed ? u : c;
+    v[it] = (i < fan_in && o < O) ? W[(int64_t)o * fan_in + i] : 0.f;
+  }
+#pragma unroll
+  for (int it = 0; it < kRounds; ++it) {
+    const int k = it * kHT + (int)threadIdx.x;
+    dst[k / kHW][k % kHW] = v[it];
+  }
+}
+
 // out[r][o] = act(b[o] + sum_i W[o][i] in[r][i]) for O <= 64 outputs (W [O][fan_in], master
-// layout); act = ReLU, or none for the heads, whose two logits go to out0 / out1.
+// layout); act = ReLU, or none for the heads, whose two logits go to out0 / out1.  S lanes share
+// a ray, lane s computing outputs s OL .. s OL + OL - 1, each summed over i in increasing
+// order: the split changes no rounding, it only spreads a batch over S times the workgroups.
+// The heads run with S = 1, OL = 2 (only the two logits are formed).
+template <int S, int OL>
 __global__ __launch_bounds__(kHT) void dense_fwd_kernel(const float* in, const float* W, const float* b, int O,
                                                         int fan_in, int64_t R, int relu, float* out, float* out0,
                                                         float* out1) {
+  static_assert(S * OL <= kHW && kHT % S == 0, "lane split");
   __shared__ __attribute__((aligned(16))) float wt[kHIn][kHW];   // transposed, zero padded
   __shared__ float bs[kHW];
-  for (int k = threadIdx.x; k < kHIn * kHW; k += blockDim.x) {
-    const int i = k / kHW, o = k % kHW;
-    wt[i][o] = (i < fan_in && o < O) ? W[(int64_t)o * fan_in + i] : 0.f;
-  }
+  stage_weights<true>(W, O, fan_in, wt);
   for (int o = threadIdx.x; o < kHW; o += blockDim.x) bs[o] = o < O ? b[o] : 0.f;
   __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * (kHT / S) + threadIdx.x / S;
   if (r >= R) return;
-  float acc[kHW];
+  const int o0 = (int)(threadIdx.x % S) * OL;
+  float acc[OL];
 #pragma unroll
-  for (int o = 0; o < kHW; ++o) acc[o] = bs[o];
+  for (int j = 0; j < OL; ++j) acc[j] = bs[o0 + j];
   const f32x4* src = reinterpret_cast<const f32x4*>(in + r * kHIn);
-  for (int q = 0; q < kHIn / 4; ++q) {
+#pragma unroll 2
+  for (int q = 0; q < kHIn / 4; ++q) {   // (fully unrolled, the weight reads all hoist: 272 VGPRs)
     const f32x4 x4 = src[q];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) axpy_row(wt[4 * q + e], x4[e], acc);
+    for (int e = 0; e < 4; ++e) axpy_n<OL>(&wt[4 * q + e][o0], x4[e], acc);
   }
   if (out) {
+    f32x4* dst = reinterpret_cast<f32x4*>(out + r * kHW + o0);
 #pragma unroll
-    for (int o = 0; o < kHW; ++o) acc[o] = relu ? fmaxf(acc[o], 0.f) : acc[o];
-    store_row(out + r * kHW, acc);
+    for (int m = 0; m < OL / 4; ++m) {
+      f32x4 y;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) y[e] = relu ? fmaxf(acc[4 * m + e], 0.f) : acc[4 * m + e];
+      dst[m] = y;
+    }
   } else {
     out0[r] = acc[0];
     out1[r] = acc[1];
@@ -696,42 +737,45 @@ __global__ __launch_bounds__(kHT) void dense_fwd_kernel(const float* in, const f
 
 // d_in[r][i] = mask(in[r][i] > 0) sum_o W[o][i] d_out[r][o] for the hidden layers (W [O][fan_in]
 // master layout, d_out [R][64]); `mask_src` null: no mask.  With dz0 / dz1 set, d_out is the
-// pair of logit gradients instead (the heads).
+// pair of logit gradients instead (the heads).  S lanes share a ray, lane s forming inputs
+// s IL .. s IL + IL - 1, each summed over o in increasing order (no rounding changes).
+template <int S, int IL>
 __global__ __launch_bounds__(kHT) void dense_bwd_kernel(const float* d_out, const float* dz0, const float* dz1,
                                                         const float* W, int O, int fan_in, int64_t R,
                                                         const float* mask_src, float* d_in) {
+  static_assert(S * IL == kHIn && IL % 4 == 0 && kHT % S == 0, "lane split");
   __shared__ __attribute__((aligned(16))) float wr[kHW][kHIn];   // rows of W, zero padded
-  for (int k = threadIdx.x; k < kHW * kHIn; k += blockDim.x) {
-    const int o = k / kHIn, i = k % kHIn;
-    wr[o][i] = (o < O && i < fan_in) ? W[(int64_t)o * fan_in + i] : 0.f;
-  }
+  stage_weights<false>(W, O, fan_in, wr);
   __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * (kHT / S) + threadIdx.x / S;
   if (r >= R) return;
-  float acc[kHIn];
+  const int i0 = (int)(threadIdx.x % S) * IL;
+  float acc[IL];
 #pragma unroll
-  for (int i = 0; i < kHIn; ++i) acc[i] = 0.f;
+  for (int j = 0; j < IL; ++j) acc[j] = 0.f;
   if (dz0) {
-    axpy_row(wr[0], dz0[r], acc);
-    axpy_row(wr[1], dz1[r], acc);
+    axpy_n<IL>(&wr[0][i0], dz0[r], acc);
+    axpy_n<IL>(&wr[1][i0], dz1[r], acc);
   } else {
     const f32x4* src = reinterpret_cast<const f32x4*>(d_out + r * kHW);
     for (int q = 0; q < kHW / 4; ++q) {
       const f32x4 d4 = src[q];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) axpy_row(wr[4 * q + e], d4[e], acc);
+      for (int e = 0; e < 4; ++e) axpy_n<IL>(&wr[4 * q + e][i0], d4[e], acc);
     }
   }
   if (mask_src) {
-    const f32x4* m4 = reinterpret_cast<const f32x4*>(mask_src + r * kHIn);
+    const f32x4* m4 = reinterpret_cast<const f32x4*>(mask_src + r * kHIn + i0);
 #pragma unroll
-    for (int q = 0; q < kHIn / 4; ++q) {
+    for (int q = 0; q < IL / 4; ++q) {
       const f32x4 h4 = m4[q];
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[4 * q + e] = h4[e] > 0.f ? acc[4 * q + e] : 0.f;
     }
   }
-  store_row(d_in + r * kHIn, acc);
+  f32x4* dst = reinterpret_cast<f32x4*>(d_in + r * kHIn + i0);
+#pragma unroll
+  for (int q = 0; q < IL / 4; ++q) dst[q] = f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
 }
 
 // The position-code gradient dg [R][64] (first 2 NL entries) of every live ray scattered to
@@ -1039,17 +1083,23 @@ int ddf_hash_train_step(const ddf_hash_desc* d, float* params, float* adam_m, fl
   const float* P = params;
   // forward through memory
   if ((rc = run_hash_encode(a, st))) return rc;
-  dense_fwd_kernel<<<rb, kHT, 0, st>>>(G, P + L.w_off[0], P + L.b_off[0], kHW, L.d_in, w.R, 1, H1, nullptr, nullptr);
-  dense_fwd_kernel<<<rb, kHT, 0, st>>>(H1, P + L.w_off[1], P + L.b_off[1], kHW, kHW, w.R, 1, H2, nullptr, nullptr);
-  dense_fwd_kernel<<<rb, kHT, 0, st>>>(H2, P + L.wh_off, P + L.bh_off, 2, kHW, w.R, 0, nullptr, zt, zx);
+  // hidden layers: 4 lanes per ray (16 outputs each); heads: one lane per ray, two outputs
+  constexpr int kDS = 4;
+  const unsigned rb4 = (unsigned)((w.R + kHT / kDS - 1) / (kHT / kDS));
+  dense_fwd_kernel<kDS, kHW / kDS><<<rb4, kHT, 0, st>>>(G, P + L.w_off[0], P + L.b_off[0], kHW, L.d_in, w.R, 1, H1,
+                                                        nullptr, nullptr);
+  dense_fwd_kernel<kDS, kHW / kDS><<<rb4, kHT, 0, st>>>(H1, P + L.w_off[1], P + L.b_off[1], kHW, kHW, w.R, 1, H2,
+                                                        nullptr, nullptr);
+  dense_fwd_kernel<1, 2><<<rb, kHT, 0, st>>>(H2, P + L.wh_off, P + L.bh_off, 2, kHW, w.R, 0, nullptr, zt, zx);
   if ((rc = hip_status(hipGetLastError(), "hash training forward launch"))) return rc;
   if ((rc = launch_ddf_loss(zt, zx, t_gt, hit_gt, batch, w.R, reinterpret_cast<float*>(wb + w.lossp),
                             reinterpret_cast<float*>(wb + w.scal), loss_out, dzt, dzx, hp->bce_weight, hp->l1_clamp, st)))
     return rc;
   // backward: deltas, then the code gradient, its scatter into the table, the weight gradients
-  dense_bwd_kernel<<<rb, kHT, 0, st>>>(nullptr, dzt, dzx, P + L.wh_off, 2, kHW, w.R, H2, D2);
-  dense_bwd_kernel<<<rb, kHT, 0, st>>>(D2, nullptr, nullptr, P + L.w_off[1], kHW, kHW, w.R, H1, D1);
-  dense_bwd_kernel<<<rb, kHT, 0, st>>>(D1, nullptr, nullptr, P + L.w_off[0], kHW, L.d_in, w.R, nullptr, DG);
+  dense_bwd_kernel<kDS, kHIn / kDS><<<rb4, kHT, 0, st>>>(nullptr, dzt, dzx, P + L.wh_off, 2, kHW, w.R, H2, D2);
+  dense_bwd_kernel<kDS, kHIn / kDS><<<rb4, kHT, 0, st>>>(D2, nullptr, nullptr, P + L.w_off[1], kHW, kHW, w.R, H1, D1);
+  dense_bwd_kernel<kDS, kHIn / kDS><<<rb4, kHT, 0, st>>>(D1, nullptr, nullptr, P + L.w_off[0], kHW, L.d_in, w.R,
+                                                         nullptr, DG);
   fill_zero_kernel<<<1024, 256, 0, st>>>(grad, 2 * L.entries);
   if ((rc = hip_status(hipGetLastError(), "hash backward launch"))) return rc;
   if ((rc = run_hash_scatter(a, DG, st))) return rc;
