@@ -823,43 +823,86 @@ __global__ __launch_bounds__(kHT) void hash_scatter_kernel(HashArgs a, const flo
   }
 }
 
-// part[blk][o I + i] = sum over the block's rays of d[r][o] a[r][i]; part[blk][O I + o] =
-// sum of d[r][o] (bias), for ray-major d [R][ldd] (first O columns) and a [R][64].  Fixed order.
-__global__ __launch_bounds__(kHT) void outer_reduce_kernel(const float* d, int ldd, const float* a, int O, int I,
+// part[blk][o 64 + i] = sum over the block's kHRC rays of d[r][o] a[r][i]; part[blk][64 O + o]
+// = sum of d[r][o] (the bias), for ray-major d [R][ldd] (first O columns, O = 64 or 1) and
+// a [R][64].  Every sum runs over the block's rays in increasing order.  Thread t owns row
+// o = t / 4 and columns 16 (t % 4) .. 16 (t % 4) + 15: one d read and four 16-byte a reads
+// per 16 products; the threads with t % 4 == 0 also form the bias sum.
+__global__ __launch_bounds__(kHT) void outer_reduce_kernel(const float* d, int ldd, const float* a, int O,
                                                            float* part) {
-  __shared__ float sd[kHRC][kHW + 1], sa[kHRC][kHIn + 1];
+  static_assert(kHT == 4 * kHW && kHIn == 64 && kHW == 64, "thread t: row t / 4, 16 columns");
+  __shared__ float sd[kHRC][kHW + 1];
+  __shared__ __attribute__((aligned(16))) float sa[kHRC][kHIn + 4];
   const int64_t r0 = (int64_t)blockIdx.x * kHRC;
-  for (int k = threadIdx.x; k < kHRC * O; k += blockDim.x) sd[k / O][k % O] = d[(r0 + k / O) * ldd + k % O];
-  for (int k = threadIdx.x; k < kHRC * I; k += blockDim.x) sa[k / I][k % I] = a[(r0 + k / I) * kHIn + k % I];
-  __syncthreads();
-  const int nout = O * I + O;
-  float* dst = part + (int64_t)blockIdx.x * nout;
-  for (int k = threadIdx.x; k < nout; k += blockDim.x) {
-    float acc = 0.f;
-    if (k < O * I) {
-      const int o = k / I, i = k % I;
-      for (int r = 0; r < kHRC; ++r) acc = fmaf(sd[r][o], sa[r][i], acc);
-    } else {
-      const int o = k - O * I;
-      for (int r = 0; r < kHRC; ++r) acc += sd[r][o];
+  const int t = threadIdx.x;
+  {
+    // the block's a rows are one contiguous kHRC x 64 slab: 16-byte loads, all issued first
+    constexpr int kA = kHRC * kHIn / 4 / kHT;
+    f32x4 v[kA];
+    const f32x4* src = reinterpret_cast<const f32x4*>(a + r0 * kHIn);
+#pragma unroll
+    for (int u = 0; u < kA; ++u) v[u] = src[u * kHT + t];
+#pragma unroll
+    for (int u = 0; u < kA; ++u) {
+      const int e = (u * kHT + t) * 4;
+      *reinterpret_cast<f32x4*>(&sa[e / kHIn][e % kHIn]) = v[u];
     }
-    dst[k] = acc;
   }
+  {
+    constexpr int kD = kHRC * kHW / kHT;
+    float v[kD];
+#pragma unroll
+    for (int u = 0; u < kD; ++u) {
+      const int e = u * kHT + t, r = e / kHW, o = e % kHW;
+      v[u] = o < O ? d[(r0 + r) * ldd + o] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < kD; ++u) {
+      const int e = u * kHT + t;
+      sd[e / kHW][e % kHW] = v[u];
+    }
+  }
+  __syncthreads();
+  const int o = t >> 2, i0 = (t & 3) * 16;
+  if (o >= O) return;
+  float acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+  float bsum = 0.f;
+  for (int r = 0; r < kHRC; ++r) {
+    const float dv = sd[r][o];
+    const f32x4* a4 = reinterpret_cast<const f32x4*>(&sa[r][i0]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const f32x4 x = a4[q];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[4 * q + e] = fmaf(dv, x[e], acc[4 * q + e]);
+    }
+    bsum += dv;
+  }
+  float* dst = part + (int64_t)blockIdx.x * (O * kHIn + O);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) dst[o * kHIn + i0 + j] = acc[j];
+  if ((t & 3) == 0) dst[O * kHIn + o] = bsum;
 }
 
 // out[k] = sum over blocks b of part[b][k], in a fixed order: eight running sums over
-// b = j (mod 8), then a pairwise tree of the eight (eight loads in flight per thread).
-__global__ void sum_parts_kernel(const float* part, int nblk, int stride, float* out) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= stride) return;
-  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  int b = 0;
-  for (; b + 8 <= nblk; b += 8) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) s[j] += part[(int64_t)(b + j) * stride + k];
+// b = j (mod 8), each in increasing b, then a pairwise tree of the eight.  Thread (j, k) runs
+// chain j of output k (its loads independent of one another); a block of 256 threads covers
+// 32 outputs x 8 chains.
+__global__ __launch_bounds__(256) void sum_parts_kernel(const float* part, int nblk, int stride, float* out) {
+  __shared__ float s[8][33];
+  const int kl = threadIdx.x & 31, j = threadIdx.x >> 5;
+  const int k = blockIdx.x * 32 + kl;
+  float acc = 0.f;
+  if (k < stride) {
+#pragma unroll 8
+    for (int b = j; b < nblk; b += 8) acc += part[(int64_t)b * stride + k];
   }
-  for (int j = 0; b + j < nblk; ++j) s[j] += part[(int64_t)(b + j) * stride + k];
-  out[k] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  s[j][kl] = acc;
+  __syncthreads();
+  if (j == 0 && k < stride)
+    out[k] = ((s[0][kl] + s[1][kl]) + (s[2][kl] + s[3][kl])) + ((s[4][kl] + s[5][kl]) + (s[6][kl] + s[7][kl]));
 }
 
 __global__ void fill_zero_kernel(float* p, int64_t n) {
@@ -1110,14 +1153,14 @@ int ddf_hash_train_step(const ddf_hash_desc* d, float* params, float* adam_m, fl
   const float* ain[2] = {G, H1};
   for (int l = 0; l < 2; ++l) {
     const int fan_in = l == 0 ? L.d_in : kHW;
-    outer_reduce_kernel<<<nblk, kHT, 0, st>>>(din[l], kHW, ain[l], kHW, kHIn, part);
-    sum_parts_kernel<<<(unsigned)((kHW * kHIn + kHW + 255) / 256), 256, 0, st>>>(part, (int)nblk, kHW * kHIn + kHW, layer);
+    outer_reduce_kernel<<<nblk, kHT, 0, st>>>(din[l], kHW, ain[l], kHW, part);
+    sum_parts_kernel<<<(unsigned)((kHW * kHIn + kHW + 31) / 32), 256, 0, st>>>(part, (int)nblk, kHW * kHIn + kHW, layer);
     scatter_layer_grad_kernel<<<(unsigned)((kHW * fan_in + kHW + 255) / 256), 256, 0, st>>>(
         layer, kHW, kHIn, fan_in, grad + L.w_off[l], grad + L.b_off[l]);
   }
   for (int o = 0; o < 2; ++o) {   // the heads: each logit gradient against H2
-    outer_reduce_kernel<<<nblk, kHT, 0, st>>>(o == 0 ? dzt : dzx, 1, H2, 1, kHIn, part);
-    sum_parts_kernel<<<(unsigned)((kHIn + 1 + 255) / 256), 256, 0, st>>>(part, (int)nblk, kHIn + 1, layer);
+    outer_reduce_kernel<<<nblk, kHT, 0, st>>>(o == 0 ? dzt : dzx, 1, H2, 1, part);
+    sum_parts_kernel<<<(unsigned)((kHIn + 1 + 31) / 32), 256, 0, st>>>(part, (int)nblk, kHIn + 1, layer);
     scatter_layer_grad_kernel<<<1, 256, 0, st>>>(layer, 1, kHIn, kHW, grad + L.wh_off + o * kHW, grad + L.bh_off + o);
   }
   if ((rc = hip_status(hipGetLastError(), "hash weight-gradient launch"))) return rc;
