@@ -601,12 +601,18 @@ __global__ __launch_bounds__(kHT) void hash_mlp_kernel(HashArgs a, const float* 
 // ---- training: one simple kernel per stage, activations in memory ([R][64] per layer)
 
 // The input code of every ray (rows n .. R - 1: the code of the box centre, zero direction).
+// kESub lanes share a ray: lane s looks up the levels l = s (mod kESub) and forms the
+// direction bands k = s (mod kESub); lane 0 also writes the raw direction and the zero
+// padding.  Each feature is computed as with one lane per ray (bit-identical); the split
+// only spreads a training batch over more workgroups.
+constexpr int kESub = 4;
 template <int NL, int NB>
 __global__ __launch_bounds__(kHT) void hash_encode_kernel(HashArgs a) {
   __shared__ LevelTab lt;
   stage_levels(a.L, lt);
   __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = threadIdx.x % kESub;
+  const int64_t r = (int64_t)blockIdx.x * (kHT / kESub) + threadIdx.x / kESub;
   if (r >= a.R) return;
   float x[3] = {0.f, 0.f, 0.f}, dv[3] = {0.f, 0.f, 0.f};
   if (r < a.n) {
@@ -616,42 +622,47 @@ __global__ __launch_bounds__(kHT) void hash_encode_kernel(HashArgs a) {
   float p[3];
   unit_point(lt, x, p);
   const float2* tab = reinterpret_cast<const float2*>(a.params);
-  float g[kHIn];
+  float* dst = a.acts + r * kHIn;
 #pragma unroll
-  for (int l = 0; l < NL; ++l) {
-    uint32_t c[3];
-    float w[3];
-    cell((float)lt.res[l], p, c, w);
-    float f0 = 0.f, f1 = 0.f;
+  for (int j = 0; j < (NL + kESub - 1) / kESub; ++j) {
+    const int l = s + kESub * j;
+    if (l < NL) {
+      uint32_t c[3];
+      float w[3];
+      cell((float)lt.res[l], p, c, w);
+      float f0 = 0.f, f1 = 0.f;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      int64_t e;
-      float wt;
-      corner(lt, l, c, w, k, e, wt);
-      const float2 t = tab[e];
-      f0 = fmaf(wt, t.x, f0);
-      f1 = fmaf(wt, t.y, f1);
+      for (int k = 0; k < 8; ++k) {
+        int64_t e;
+        float wt;
+        corner(lt, l, c, w, k, e, wt);
+        const float2 t = tab[e];
+        f0 = fmaf(wt, t.x, f0);
+        f1 = fmaf(wt, t.y, f1);
+      }
+      *reinterpret_cast<float2*>(dst + 2 * l) = make_float2(f0, f1);
     }
-    g[2 * l] = f0;
-    g[2 * l + 1] = f1;
   }
   constexpr int D0 = 2 * NL;
+  if (s == 0) {
 #pragma unroll
-  for (int q = 0; q < 3; ++q) g[D0 + q] = dv[q];
+    for (int q = 0; q < 3; ++q) dst[D0 + q] = dv[q];
 #pragma unroll
-  for (int k = 0; k < NB; ++k)
+    for (int i = D0 + 3 * (1 + 2 * NB); i < kHIn; ++i) dst[i] = 0.f;
+  }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      float sn, cs;
-      sincospif(ldexpf(dv[q], k), &sn, &cs);
-      g[D0 + 3 + 6 * k + q] = sn;
-      g[D0 + 6 + 6 * k + q] = cs;
+  for (int j = 0; j < (NB + kESub - 1) / kESub; ++j) {
+    const int k = s + kESub * j;
+    if (k < NB) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        float sn, cs;
+        sincospif(ldexpf(dv[q], k), &sn, &cs);
+        dst[D0 + 3 + 6 * k + q] = sn;
+        dst[D0 + 6 + 6 * k + q] = cs;
+      }
     }
-#pragma unroll
-  for (int i = D0 + 3 * (1 + 2 * NB); i < kHIn; ++i) g[i] = 0.f;
-  f32x4* dst = reinterpret_cast<f32x4*>(a.acts + r * kHIn);
-#pragma unroll
-  for (int q = 0; q < kHIn / 4; ++q) dst[q] = f32x4{g[4 * q], g[4 * q + 1], g[4 * q + 2], g[4 * q + 3]};
+  }
 }
 
 // h[j] += row[j] v, j < N (row: N consecutive weights in LDS, 16-byte aligned when N % 4 == 0).
@@ -978,7 +989,8 @@ int run_hash_forward(const HashLayout& L, const float* params, const float* rays
 // The training pass after the forward (stages in memory, [R][64] per layer, R a multiple of
 // 64): G = code, H1, H2; D2, D1, DG the deltas and the code gradient.
 int run_hash_encode(const HashArgs& a, hipStream_t st) {
-  const unsigned blocks = (unsigned)((a.R + kHT - 1) / kHT);
+  constexpr int rays_per_block = kHT / kESub;
+  const unsigned blocks = (unsigned)((a.R + rays_per_block - 1) / rays_per_block);
   if (a.L.n_levels == 16)
     hash_encode_kernel<16, 4><<<blocks, kHT, 0, st>>>(a);
   else
