@@ -897,11 +897,14 @@ __global__ __launch_bounds__(kHT) void outer_reduce_kernel(const float* d, int l
   if ((t & 3) == 0) dst[O * kHIn + o] = bsum;
 }
 
-// out[k] = sum over blocks b of part[b][k], in a fixed order: eight running sums over
+// v[k] = sum over blocks b of part[b][k], in a fixed order: eight running sums over
 // b = j (mod 8), each in increasing b, then a pairwise tree of the eight.  Thread (j, k) runs
 // chain j of output k (its loads independent of one another); a block of 256 threads covers
-// 32 outputs x 8 chains.
-__global__ __launch_bounds__(256) void sum_parts_kernel(const float* part, int nblk, int stride, float* out) {
+// 32 outputs x 8 chains.  The sums go straight to the master layout: k = 64 o + i to
+// w[o fan_in + i] (the padding columns i >= fan_in are dropped), k = 64 O + o to b[o].
+__global__ __launch_bounds__(256) void sum_parts_kernel(const float* part, int nblk, int O, int fan_in, float* w,
+                                                        float* b) {
+  const int stride = O * kHIn + O;
   __shared__ float s[8][33];
   const int kl = threadIdx.x & 31, j = threadIdx.x >> 5;
   const int k = blockIdx.x * 32 + kl;
@@ -912,29 +915,22 @@ __global__ __launch_bounds__(256) void sum_parts_kernel(const float* part, int n
   }
   s[j][kl] = acc;
   __syncthreads();
-  if (j == 0 && k < stride)
-    out[k] = ((s[0][kl] + s[1][kl]) + (s[2][kl] + s[3][kl])) + ((s[4][kl] + s[5][kl]) + (s[6][kl] + s[7][kl]));
+  if (j == 0 && k < stride) {
+    const float v = ((s[0][kl] + s[1][kl]) + (s[2][kl] + s[3][kl])) + ((s[4][kl] + s[5][kl]) + (s[6][kl] + s[7][kl]));
+    if (k >= O * kHIn)
+      b[k - O * kHIn] = v;
+    else if (k % kHIn < fan_in)
+      w[(k / kHIn) * fan_in + k % kHIn] = v;
+  }
 }
 
 __global__ void fill_zero_kernel(float* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.f;
 }
 
-// Weight-gradient rows of a layer in the master layout: W [o][fan_in] then b [o].
-__global__ void scatter_layer_grad_kernel(const float* src /*[O*I + O], inputs padded to I*/, int O, int I, int fan_in,
-                                          float* w, float* b) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < O * fan_in) {
-    const int o = k / fan_in, i = k % fan_in;
-    w[k] = src[o * I + i];
-  } else if (k < O * fan_in + O) {
-    b[k - O * fan_in] = src[O * I + (k - O * fan_in)];
-  }
-}
-
 struct HashWs {
   int64_t R;
-  int64_t zt, zx, dzt, dzx, lossp, scal, acts, deltas, part, layer, grad, total;
+  int64_t zt, zx, dzt, dzx, lossp, scal, acts, deltas, part, grad, total;
 };
 
 HashWs hash_ws(const HashLayout& L, int64_t batch) {
@@ -948,7 +944,6 @@ HashWs hash_ws(const HashLayout& L, int64_t batch) {
   w.acts = take(4ll * 3 * kHIn * w.R);     // G, H1, H2
   w.deltas = take(4ll * 3 * kHIn * w.R);   // D2, D1, DG
   w.part = take(4ll * (w.R / kHRC) * (kHW * kHIn + kHW));
-  w.layer = take(4ll * (kHW * kHIn + kHW));
   w.grad = take(4 * L.params);
   w.total = off;
   return w;
@@ -1160,20 +1155,18 @@ int ddf_hash_train_step(const ddf_hash_desc* d, float* params, float* adam_m, fl
   if ((rc = run_hash_scatter(a, DG, st))) return rc;
   const unsigned nblk = (unsigned)(w.R / kHRC);
   float* part = reinterpret_cast<float*>(wb + w.part);
-  float* layer = reinterpret_cast<float*>(wb + w.layer);
   const float* din[2] = {D1, D2};
   const float* ain[2] = {G, H1};
   for (int l = 0; l < 2; ++l) {
     const int fan_in = l == 0 ? L.d_in : kHW;
     outer_reduce_kernel<<<nblk, kHT, 0, st>>>(din[l], kHW, ain[l], kHW, part);
-    sum_parts_kernel<<<(unsigned)((kHW * kHIn + kHW + 31) / 32), 256, 0, st>>>(part, (int)nblk, kHW * kHIn + kHW, layer);
-    scatter_layer_grad_kernel<<<(unsigned)((kHW * fan_in + kHW + 255) / 256), 256, 0, st>>>(
-        layer, kHW, kHIn, fan_in, grad + L.w_off[l], grad + L.b_off[l]);
+    sum_parts_kernel<<<(unsigned)((kHW * kHIn + kHW + 31) / 32), 256, 0, st>>>(part, (int)nblk, kHW, fan_in,
+                                                                                grad + L.w_off[l], grad + L.b_off[l]);
   }
   for (int o = 0; o < 2; ++o) {   // the heads: each logit gradient against H2
     outer_reduce_kernel<<<nblk, kHT, 0, st>>>(o == 0 ? dzt : dzx, 1, H2, 1, part);
-    sum_parts_kernel<<<(unsigned)((kHIn + 1 + 31) / 32), 256, 0, st>>>(part, (int)nblk, kHIn + 1, layer);
-    scatter_layer_grad_kernel<<<1, 256, 0, st>>>(layer, 1, kHIn, kHW, grad + L.wh_off + o * kHW, grad + L.bh_off + o);
+    sum_parts_kernel<<<(unsigned)((kHIn + 1 + 31) / 32), 256, 0, st>>>(part, (int)nblk, 1, kHW,
+                                                                       grad + L.wh_off + o * kHW, grad + L.bh_off + o);
   }
   if ((rc = hip_status(hipGetLastError(), "hash weight-gradient launch"))) return rc;
   return launch_adam_flat(params, adam_m, adam_v, grad, L.params, hp, nonfinite_flag, st);
