@@ -192,3 +192,35 @@ def test_hash_training_recipe_trains():
     l1 = held_loss()
     print(f"hash-grid recipe: held-out loss {l0:.4f} -> {l1:.4f}")
     assert int(flag.cpu()[0]) == 0 and l1 < 0.8 * l0
+
+
+def test_hash_train_step_repeatable():
+    """Two training steps of the paper's field from the same state on a ragged batch: the loss
+    and every MLP gradient are bit-identical (all their sums run in a fixed order), and the
+    table gradient agrees up to the order in which its float atomics land."""
+    dev = cuda()
+    desc = I.HASH_PAPER
+    n = 4096 + 37
+    sc = I.scene_ellipsoids(256, 3)
+    rays = I.train_rays(sc, n, 1430)
+    tg, hit, _ = G.intersect_soa(sc, rays)
+    tg = np.where(hit, tg, 0).astype(np.float32)
+    params = _params(desc, 37, table_std=0.2)
+    E2 = H.table_entries(desc) * desc.n_feat
+    ws = torch.empty(ddf.hash_train_workspace_bytes(desc, n), dtype=torch.uint8, device=dev)
+    out = []
+    for _ in range(2):
+        p = _t(params, dev)
+        m = torch.zeros_like(p); v = torch.zeros_like(p)
+        grad = torch.empty_like(p)
+        hp = ddf.TrainHParamsC(3e-3, 0.9, 0.999, 1e-8, O.BCE_WEIGHT, O.L1_CLAMP, 1)
+        loss, flag = ddf.hash_train_step(desc, p, m, v, _t(rays, dev), _t(tg, dev), _t(hit.astype(np.uint8), dev), hp,
+                                         ws, grad_out=grad)
+        torch.cuda.synchronize()
+        assert int(flag.cpu()[0]) == 0
+        out.append((loss.cpu().numpy()[:3].copy(), grad.cpu().numpy()))
+    (l_a, g_a), (l_b, g_b) = out
+    assert np.array_equal(l_a.view(np.uint32), l_b.view(np.uint32))
+    assert np.array_equal(g_a[E2:].view(np.uint32), g_b[E2:].view(np.uint32))
+    tab = np.abs(g_a[:E2]).max()
+    assert tab > 0 and np.abs(g_a[:E2] - g_b[:E2]).max() <= 1e-5 * tab
