@@ -634,10 +634,20 @@ __global__ void head_grad_final_kernel(const float* part, int W, int n_out, floa
 
 __global__ void zero_flag_kernel(int32_t* flag) { if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0; }
 
+// flag |= 1 if any g[i], i < n, is not finite.  16-byte loads over the aligned body (an
+// unaligned g takes the 4-byte loop throughout), 4-byte loads over the tail.
 __global__ void finite_check_kernel(const float* g, int64_t n, int32_t* flag) {
   bool bad = false;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    bad |= !isfinite(g[i]);
+  const int64_t n4 = (reinterpret_cast<uintptr_t>(g) & 15) ? 0 : n / 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const f32x4* g4 = reinterpret_cast<const f32x4*>(g);
+#pragma unroll 4
+  for (int64_t i = t; i < n4; i += stride) {
+    const f32x4 v = g4[i];
+    bad |= !(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(v[3]));
+  }
+  for (int64_t i = 4 * n4 + t; i < n; i += stride) bad |= !isfinite(g[i]);
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
