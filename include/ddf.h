@@ -179,13 +179,13 @@ int sdf_sphere_trace(const ddf_net_desc* desc, const void* packed, const float* 
                      int64_t n, int32_t max_steps, float hit_eps, float t_max, float* t,
                      uint8_t* hit, int32_t* steps, void* ws, size_t ws_bytes, void* stream);
 
-/* The small-batch query (the sparse regime, ~1K rays): bf16 nets of width 256, 512
+/* The small-batch query (the sparse regime, ~1K-5K rays): bf16 nets of width 256, 512
  * or 1024 only.  One launch per layer with the layer's neurons split over workgroups (64
- * rays x 128 neurons each), so that a small batch still spreads over every CU; the
+ * rays x 256 neurons each), so that a small batch still spreads over every CU; the
  * activations pass through ws between layers.  Hidden activations are bit-identical to
  * ddf_query's; the heads' sums run in another order (float32 rounding).  ws: device,
  * >= ddf_query_split_workspace_bytes(desc, n) (else DDF_ERR_WORKSPACE), overwritten; n <=
- * 2^25.  Faster than ddf_query below ~3K rays (half the time at 1K), slower above. */
+ * 2^25.  Faster than ddf_query below ~5K rays (half the time at 1K), slower above. */
 size_t ddf_query_split_workspace_bytes(const ddf_net_desc* desc, int64_t n);
 int ddf_query_split(const ddf_net_desc* desc, const void* packed, const float* rays, int64_t n, float* t,
                     float* xi, void* ws, size_t ws_bytes, void* stream);

@@ -1,13 +1,15 @@
 // The small-batch DDF query: one launch per layer with the layer's neurons split across
 // workgroups.  The fused query gives each workgroup 64 rays and the whole network, so every
 // workgroup streams all the weights and a batch below ~16K rays leaves most CUs idle (a 1K-ray
-// query takes as long as a 10K-ray one).  Measured, this path halves the time of a 1K-ray
-// query and loses above ~3K rays (per-layer launches, activations through memory).  Here a workgroup owns 64 rays x 128 neurons of one
-// layer: a 1K-ray batch already fills 16 x (width / 128) workgroups per layer, each streaming
-// only its 128 neurons' weights; the activations go through a [rays][width] buffer (L2-
-// resident at these sizes) between layers.  The products are the fused kernel's (same operand
-// blocks, same k order), so the hidden activations are bit-identical; the heads' partial sums
-// are added in another order.
+// query takes as long as a 10K-ray one).  Here a workgroup of 8 waves owns 64 rays x 256
+// neurons of one layer: a 1K-ray batch fills 16 x (width / 256) workgroups per layer, each
+// streaming only its 256 neurons' weights; the activations go through a [rays][width] buffer
+// between layers.  Every workgroup of a ray tile reads the tile's whole input, so the
+// neuron-group count (width / 256) is also the number of times the activations are re-read,
+// the path's bound from a few thousand rays up; 8 waves rather than 4 halve those re-reads
+// and give each SIMD two waves (the 128 KiB activation tile allows one workgroup per CU).
+// The products are the fused kernel's (same operand blocks, same k order), so the hidden
+// activations are bit-identical; the heads' partial sums are added in another order.
 #include <math.h>
 
 #include "ddf_chain.h"
@@ -21,7 +23,7 @@ FwdArgs base_args(const ddf_net_desc& d, const void* packed);
 
 namespace {
 
-constexpr int kSplitWaves = 4;                       // one 32-neuron tile per wave
+constexpr int kSplitWaves = 8;                       // one 32-neuron tile per wave
 constexpr int kSplitNeurons = 32 * kSplitWaves;      // neurons per workgroup
 
 struct SplitArgs {
@@ -29,7 +31,7 @@ struct SplitArgs {
   int layer;              // 0-based hidden layer of this launch
   const __bf16* hin;      // [R][width] the layer's input (layer > 0)
   __bf16* hout;           // [R][width] the layer's output (all but the last layer)
-  float* part;            // [width / 128][R][2] head partial sums (the last layer)
+  float* part;            // [width / 256][R][2] head partial sums (the last layer)
   int64_t R;              // rows (a multiple of 64)
 };
 

@@ -108,13 +108,13 @@ def test_hash_layout_matches_oracle():
 
 def test_workspace_sizing_calls():
     """Host-side sizing: the small-batch query keeps two [R][width] bf16 activation buffers
-    (R = n rounded up to 64) and [width / 128][R][2] float head partials, each 256-byte
+    (R = n rounded up to 64) and [width / 256][R][2] float head partials, each 256-byte
     aligned; the float16 hash table is 2 halves per entry; unsupported shapes size to 0."""
     from oracle import hashgrid_oracle as H
     a256 = lambda x: (x + 255) // 256 * 256
     for n in (1, 1000, 4097):
         R = (n + 63) // 64 * 64
-        want = 2 * a256(R * 1024 * 2) + a256(8 * R * 2 * 4)
+        want = 2 * a256(R * 1024 * 2) + a256(4 * R * 2 * 4)
         assert ddf.query_split_workspace_bytes(I.NET_FULL, n) == want
     assert ddf.query_split_workspace_bytes(I.NET_TINY, 100) == 0     # width 128: not built
     import ctypes
