@@ -72,6 +72,14 @@ const char* ddf_last_error(void);
 /* Length of the float32 master parameter vector (layout above); 0 if desc is invalid. */
 size_t ddf_param_count(const ddf_net_desc* desc);
 
+/* Float offsets of one layer's weight and bias in the master vector (the layout above).
+ *   layer  0 .. n_hidden - 1: hidden layer layer + 1 (W [width][fan_in], then b [width]);
+ *          n_hidden: the head (W_head [n_out][width], then b_head [n_out]).
+ *   w_off, b_off  host, written on success.
+ * Returns DDF_ERR_INVALID_ARG (nothing written) for an invalid desc, a layer outside
+ * 0..n_hidden or a NULL output. */
+int ddf_param_offsets(const ddf_net_desc* desc, int32_t layer, size_t* w_off, size_t* b_off);
+
 /* Bytes of the packed working copy of the network for desc->precision; 0 if invalid.
  * The packed form is opaque: weights pre-arranged in matrix-core operand order,
  * fp32 biases and heads, and (FP8) the per-layer scales. */

@@ -193,6 +193,21 @@ size_t ddf_param_count(const ddf_net_desc* d) {
   return w * nf + w + (size_t)(d->n_hidden - 1) * (w * w + w) + (size_t)d->n_out * w + d->n_out;
 }
 
+int ddf_param_offsets(const ddf_net_desc* d, int32_t layer, size_t* w_off, size_t* b_off) {
+  int rc;
+  if ((rc = check_desc(d))) return rc;
+  if (layer < 0 || layer > d->n_hidden)
+    return fail(DDF_ERR_INVALID_ARG, "layer = %d must be in 0..%d (n_hidden = the head)", layer, d->n_hidden);
+  if (!w_off || !b_off) return fail(DDF_ERR_INVALID_ARG, "w_off and b_off must not be NULL");
+  const size_t nf = (size_t)d->n_in * (1 + 2 * d->n_freq);
+  const size_t w = d->width;
+  size_t off = 0;
+  for (int l = 0; l < layer; ++l) off += (l == 0 ? nf : w) * w + w;
+  *w_off = off;
+  *b_off = off + (layer == d->n_hidden ? (size_t)d->n_out * w : (layer == 0 ? nf : w) * w);
+  return DDF_OK;
+}
+
 size_t ddf_packed_bytes(const ddf_net_desc* d) {
   if (check_desc(d) != DDF_OK) return 0;
   return (size_t)make_layout(*d).total;

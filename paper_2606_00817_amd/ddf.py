@@ -57,6 +57,7 @@ SIGNATURES = {
     "ddf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "ddf_last_error": (ctypes.c_char_p, []),
     "ddf_param_count": (_SZ, [_D]),
+    "ddf_param_offsets": (ctypes.c_int, [_D, ctypes.c_int32, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ)]),
     "ddf_packed_bytes": (_SZ, [_D]),
     "ddf_pack": (ctypes.c_int, [_D, _P, ctypes.POINTER(ctypes.c_float), _P, _P]),
     "ddf_query": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P, _P]),
@@ -148,6 +149,14 @@ def _dev(t, dtype, name):
 def param_count(desc, precision=None) -> int:
     d = desc_c(desc, precision)
     return int(lib().ddf_param_count(ctypes.byref(d)))
+
+
+def param_offsets(desc, layer, precision=None):
+    """(w_off, b_off) of a layer in the master vector: 0..n_hidden-1 hidden, n_hidden the head."""
+    d = desc_c(desc, precision)
+    w, b = _SZ(), _SZ()
+    _check(lib().ddf_param_offsets(ctypes.byref(d), int(layer), ctypes.byref(w), ctypes.byref(b)))
+    return int(w.value), int(b.value)
 
 
 def packed_bytes(desc, precision) -> int:

@@ -34,6 +34,28 @@ def test_param_count_matches_master_layout():
     assert ddf.packed_bytes(I.NET_FULL, "bf16") > 0
 
 
+def test_param_offsets_match_master_layout():
+    """ddf_param_offsets against the generator's own layout (weights then bias per layer,
+    the head last) for the four workload nets, and its refusals."""
+    for desc in (I.NET_TINY, I.NET_FULL, I.NET_LARGE, I.NET_SDF):
+        offs = desc.offsets()
+        assert len(offs) == desc.n_hidden + 1
+        for layer, (w_off, b_off, _, _) in enumerate(offs):
+            assert ddf.param_offsets(desc, layer) == (w_off, b_off)
+        w_h, b_h = ddf.param_offsets(desc, desc.n_hidden)
+        assert b_h + desc.n_out == ddf.param_count(desc)
+    L = ddf.lib()
+    d = ddf.desc_c(I.NET_TINY, "fp32")
+    w, b = ctypes.c_size_t(7), ctypes.c_size_t(7)
+    for layer in (-1, I.NET_TINY.n_hidden + 1):
+        rc, msg = _err(L.ddf_param_offsets(ctypes.byref(d), layer, ctypes.byref(w), ctypes.byref(b)))
+        assert rc == -1 and "layer" in msg and w.value == 7 and b.value == 7
+    rc, msg = _err(L.ddf_param_offsets(ctypes.byref(d), 0, None, ctypes.byref(b)))
+    assert rc == -1 and "NULL" in msg
+    bad = ddf.desc_c(I.NetDesc(6, 4, 4, 100, 2))
+    assert L.ddf_param_offsets(ctypes.byref(bad), 0, ctypes.byref(w), ctypes.byref(b)) < 0
+
+
 def _err(rc):
     return rc, ddf.lib().ddf_last_error().decode()
 

@@ -280,6 +280,55 @@ def test_pow2_scale():
     assert O.pow2_scale(0.0) == 1.0
 
 
+def _gain_chain_net():
+    """A 5-layer net whose per-layer maxima are known in closed form.
+
+    Layer 1 reads the identity feature x0 with gain 240 (neuron 0) or 120 (neuron 1);
+    layer l >= 2 reads neuron 0 of layer l - 1 with gain g_l (neuron 0) or g_l / 2
+    (neuron 1); every other weight and every bias is 0.  For a calibration batch whose
+    largest x0 is 1.25 the maxima are exact binary numbers:
+      max h_1 = 300, max h_2 = 3000, max h_3 = 3000 / 4096, max h_4 = 46.875, max h_5 = 187.5
+    and the largest |W_l| (l >= 2) are 10, 2^-12, 64, 4."""
+    desc = I.NetDesc(6, 1, 5, 4, 2)
+    gains = [240.0, 10.0, 2.0 ** -12, 64.0, 4.0]
+    parts = []
+    for li, g in enumerate(gains):
+        W = np.zeros((4, desc.n_feat if li == 0 else 4))
+        W[0, 0] = g
+        W[1, 0] = g / 2
+        parts += [W.ravel(), np.zeros(4)]
+    parts += [np.ones(8), np.zeros(2)]
+    return desc, np.concatenate(parts).astype(np.float32)
+
+
+def test_fp8_scales_closed_form():
+    """The per-layer FP8 scales of the reduced-precision query (Sec. III-C; per-layer
+    power-of-two scales): the input scale of hidden layer l >= 2 comes from max h_(l-1)
+    over the calibration batch, the weight scale from max |W_l|, each the smallest power of
+    two s with max / s <= 448.  A layer shifted by one (h_2..h_n instead of h_1..h_(n-1)),
+    a max over one ray instead of the batch, or a signed instead of an absolute weight
+    maximum gives another list."""
+    desc, params = _gain_chain_net()
+    x0 = np.array([0.5, -1.0, 0.0, 1.25, 0.75, -3.0])     # largest positive x0 in the middle
+    rays = np.zeros((6, x0.size), dtype=np.float32)
+    rays[0] = x0
+    rays[5] = 1.0
+    # max h_(l-1) = 300, 3000, 0.732421875, 46.875 -> 1, 8, 2^-9, 2^-3
+    assert O.act_scales_fp8(desc, params, rays) == [1.0, 8.0, 2.0 ** -9, 2.0 ** -3]
+    # max |W_l| = 10, 2^-12, 64, 4 -> 2^-5, 2^-20, 2^-2, 2^-6
+    assert O.weight_scales_fp8(desc, params) == [2.0 ** -5, 2.0 ** -20, 2.0 ** -2, 2.0 ** -6]
+    neg = params.copy()
+    lay = desc.offsets()
+    w_off = lay[2][0]
+    neg[w_off] = -neg[w_off]          # W_3[0, 0] = -2^-12: the largest magnitude is unchanged
+    assert O.weight_scales_fp8(desc, neg)[1] == 2.0 ** -20
+    # each scale puts the layer's largest value inside e4m3's range and no power of two
+    # smaller does
+    hs, _ = O.mlp_forward(desc, params, O.encode(O.rays_to_inputs(rays), desc.n_freq))
+    for h, s in zip(hs[:-1], O.act_scales_fp8(desc, params, rays)):
+        assert h.max() / s <= 448.0 < h.max() / (s / 2)
+
+
 def _brute_emulated(desc, params, ray, precision, act_scales):
     """Element-by-element emulation with torch's own casts (independent of the oracle's rounding)."""
     def bf(x):
