@@ -10,8 +10,8 @@ What is computed (paper references by section / equation):
 * The DDF maps a ray (origin x in R^3, unit direction d) to (t, xi): the
   distance to the first surface along d and the probability that the ray
   hits at all (Sec. III-A, Eq. 1).
-* The field is the "sinusoidal encoding with a wide MLP" form (Sec. IV-C,
-  Table II): v = (x, d) is encoded as
+* The field is the sinusoidal-encoding form with a dense ReLU network of the
+  encoding comparison (Sec. IV-C, Table II): v = (x, d) is encoded as
   gamma(v) = [v, sin(pi 2^0 v), cos(pi 2^0 v), ..., sin(pi 2^(L-1) v), cos(pi 2^(L-1) v)]
   (each block holds all n_in coordinates), i.e. n_in (1 + 2L) features,
   followed by n_hidden Linear+ReLU layers (the first maps the features to the

@@ -1,8 +1,9 @@
 // FP8 (OCP e4m3) forward pass of the DDF / SDF MLP on the gfx950 matrix cores.
 //
-// Same structure as the fp32/bf16 chain (one workgroup of 4 waves owns a ray
-// tile for the whole network, activations resident in LDS, weight blocks
-// streamed from global memory), with M = 128 rays per workgroup:
+// Same structure as the fp32/bf16 chain (one workgroup owns a ray tile for the
+// whole network: 8 waves, two per SIMD, at width 512 and 1024, 4 at width 256;
+// activations resident in LDS, weight blocks streamed from global memory), with
+// M = 128 rays per workgroup:
 //  * layer 1 reads the encoded input split as bf16 hi + lo
 //    (v_mfma_f32_32x32x16_bf16) with bf16 weights;
 //  * hidden layers 2..n read e4m3 activations and e4m3 weights
@@ -10,7 +11,7 @@
 //    fp32 and rescale the sum by the layer's power-of-two s_A s_W;
 //  * the epilogue adds the bias, applies ReLU and stores e4m3(h / s_A,next)
 //    into LDS; the heads read the fp32 output of the last layer.
-// A wave owns width/4 output neurons; with 128 rays the accumulators of all of
+// A wave owns width/waves output neurons; with 128 rays the accumulators of all of
 // them do not fit at once, so each layer runs in two passes over half of the
 // wave's neurons, the first pass's e4m3 results waiting in registers until the
 // layer's input may be overwritten.

@@ -547,12 +547,13 @@ __global__ __launch_bounds__(kThreads, 1) void dw_kernel(DwArgs a) {
 }
 
 // grad[i] = sum over ray ranges s (in order) of partial[s][i], for the hidden layers' slice
-// [0, n) of the parameter vector (the head gradients are written directly).
+// [0, n) of the parameter vector (the head gradients are written directly); compensated
+// (Neumaier), so the ranges' partial sums are added with one rounding at the end.
 __global__ void sum_splits_kernel(const float* part, int splits, int64_t P, int64_t n, float* grad) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part[(int64_t)k * P + i];
-    grad[i] = s;
+    float s = 0.f, c = 0.f;
+    for (int k = 0; k < splits; ++k) kahan_add(s, c, part[(int64_t)k * P + i]);
+    grad[i] = s + c;
   }
 }
 

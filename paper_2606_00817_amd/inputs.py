@@ -218,6 +218,30 @@ def _inside_any(scene: Scene, p: np.ndarray, exclude=None) -> np.ndarray:
     return inside
 
 
+def _inside_other(scene: Scene, p: np.ndarray, k: np.ndarray) -> np.ndarray:
+    """Is the point p[i], drawn on the surface of primitive k[i], inside another primitive?
+
+    The same test as _inside_any(scene, p, exclude=k), organised per primitive: a point of
+    primitive a can only lie inside a primitive j whose bounding ball meets a's, so each
+    primitive's points are tested against those neighbours alone."""
+    inside = np.zeros(len(p), dtype=bool)
+    rad = scene.axes.max(axis=1) * 1.0001
+    dist = np.linalg.norm(scene.centers[:, None, :] - scene.centers[None, :, :], axis=2)
+    order = np.argsort(k, kind="stable")
+    bounds = np.searchsorted(k[order], np.arange(scene.n + 1))
+    for a in range(scene.n):
+        idx = order[bounds[a]:bounds[a + 1]]
+        if idx.size == 0:
+            continue
+        pa = p[idx]
+        for j in np.nonzero(dist[a] <= rad[a] + rad)[0]:
+            if j == a:
+                continue
+            loc = ((pa - scene.centers[j]) @ scene.rot[j]) / scene.axes[j]
+            inside[idx[np.einsum('ni,ni->n', loc, loc) < 1.0]] = True
+    return inside
+
+
 def _unit_sphere_dirs(rng, n):
     z = 1.0 - 2.0 * rng.uniform(size=n)
     phi = 2.0 * np.pi * rng.uniform(size=n)
@@ -262,7 +286,7 @@ def surface_points(scene: Scene, n: int, seed: int):
         p = scene.centers[k] + np.einsum('mij,mj->mi', R, a * u)
         nrm = np.einsum('mij,mj->mi', R, u / a)
         nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
-        keep = ~_inside_any(scene, p, exclude=k)
+        keep = ~_inside_other(scene, p, k)
         ps.append(p[keep]); ns.append(nrm[keep]); have += int(keep.sum())
     return np.concatenate(ps)[:n], np.concatenate(ns)[:n]
 
