@@ -105,6 +105,20 @@ int ddf_pack(const ddf_net_desc* desc, const float* master, const float* act_sca
 int ddf_query(const ddf_net_desc* desc, const void* packed, const float* rays, int64_t n,
               float* t, float* xi, void* stream);
 
+/* The last hidden layer's activations, h_n = relu(W_n h_(n-1) + b_n) in float32 exactly as
+ * the heads of ddf_query read them (before any rounding to the next layer's operand type),
+ * for inspection of one layer at a time: querying the network cut after layer l (the first l
+ * hidden layers of a master vector, any head, packed with n_hidden = l and, for FP8, the
+ * first l - 1 activation scales) gives the kernel's own h_l, and the layer above it is then
+ * checked in isolation against its definition (Sec. III-A network, Sec. III-C reduced
+ * precision).
+ *   packed  device, from ddf_pack with the same desc.
+ *   in      device float32 [n_in][n] SoA (rays, or points for n_in 3).
+ *   h       device float32 [n][width], row per ray, written.
+ * Same launch shape and arithmetic as ddf_query / sdf_eval on the same desc. */
+int ddf_query_hidden(const ddf_net_desc* desc, const void* packed, const float* in, int64_t n,
+                     float* h, void* stream);
+
 /* Per-layer power-of-two FP8 input scales from a calibration batch (host result).
  * Runs the float32 forward of `master` (desc with precision DDF_FP32 semantics) over
  * `rays` [6][n] and returns in act_scales_host[0 .. n_hidden-2] the smallest power of
@@ -153,6 +167,17 @@ int ddf_forward_train(const ddf_net_desc* desc, const void* packed, const float*
 int ddf_backward(const ddf_net_desc* desc, const void* packed, const float* rays, int64_t n,
                  const float* grad_z_t, const float* grad_z_xi, float* grad_params,
                  int32_t recompute_every, void* ws, size_t ws_bytes, void* stream);
+
+/* The activation H_layer (1 <= layer <= n_hidden, post-ReLU) that ddf_forward_train kept in
+ * ws for n rays, as float32 [n][width] (device, written): the values the backward pass reads,
+ * in the operand type they were kept in (bf16 for the reduced precisions), so that H > 0 are
+ * the ReLU masks the backward pass applies (Sec. III-B distillation; for inspecting one
+ * layer of the training path).  desc, n and recompute_every as for the forward call; with
+ * recomputation only checkpoint layers (multiples of k, and n_hidden) are kept, any other
+ * layer is DDF_ERR_INVALID_ARG.  ws must still hold that forward pass's activations. */
+int ddf_train_kept_activation(const ddf_net_desc* desc, int64_t n, int32_t recompute_every,
+                              const void* ws, size_t ws_bytes, int32_t layer, float* h,
+                              void* stream);
 
 /* One distillation step (Sec. III-B, III-D): forward, loss, backward, Adam, repack.
  *   loss = mean over hit rays of min(|softplus(z_t) - t_gt|, l1_clamp)

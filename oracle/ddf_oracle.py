@@ -202,6 +202,25 @@ def act_scales_fp8(desc, params, calib_rays):
     return [pow2_scale(float(np.max(h))) for h in hs[:-1]]
 
 
+def hidden_layer_emulated(W, b, x, precision, s_a=None, s_w=None):
+    """One hidden layer l >= 2 from its input x [N, width] with the kernels' roundings.
+
+    'fp32': relu(x W^T + b), no rounding.  'bf16': relu(bf16(x) bf16(W)^T + b).
+    'fp8': relu((e4m3(x / s_a) e4m3(W / s_w)^T) s_a s_w + b) with power-of-two scales.
+    Products and sums exact (float64: every product of two bf16 or e4m3 values is exact,
+    and a 1024-term sum of them loses nothing measurable against float32)."""
+    x = np.asarray(x, dtype=np.float64)
+    if precision == 'fp32':
+        a = x @ W.T + b
+    elif precision == 'bf16':
+        a = round_bf16(x) @ round_bf16(W).T + b
+    elif precision == 'fp8':
+        a = (round_e4m3(x / s_a) @ round_e4m3(W / s_w).T) * (s_a * s_w) + b
+    else:
+        raise ValueError(precision)
+    return np.maximum(a, 0.0)
+
+
 def mlp_forward_emulated(desc, params, gamma, precision, act_scales=None):
     """Forward pass with the kernels' roundings, every other operation exact (float64).
 
@@ -223,14 +242,12 @@ def mlp_forward_emulated(desc, params, gamma, precision, act_scales=None):
     hs = [h]
     sw = weight_scales_fp8(desc, params) if precision == 'fp8' else None
     for li, (W, b) in enumerate(L[1:-1]):
-        if precision == 'bf16':
-            a = round_bf16(h) @ round_bf16(W).T + b
-        elif precision == 'fp8':
-            sa = act_scales[li]
-            a = (round_e4m3(h / sa) @ round_e4m3(W / sw[li]).T) * (sa * sw[li]) + b
+        if precision == 'fp8':
+            h = hidden_layer_emulated(W, b, h, 'fp8', act_scales[li], sw[li])
+        elif precision == 'bf16':
+            h = hidden_layer_emulated(W, b, h, 'bf16')
         else:
             raise ValueError(precision)
-        h = np.maximum(a, 0.0)
         hs.append(h)
     Wh, bh = L[-1]
     return hs, h @ Wh.T + bh

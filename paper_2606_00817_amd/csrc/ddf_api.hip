@@ -45,8 +45,6 @@ int check_desc(const ddf_net_desc* d) {
   Layout L = make_layout(*d);
   if (L.k1 > d->width)
     return fail(DDF_ERR_UNSUPPORTED, "padded layer-1 input (%d) wider than the hidden width (%d)", L.k1, d->width);
-  if (d->precision == DDF_FP8_E4M3 && d->n_hidden < 2)
-    return fail(DDF_ERR_UNSUPPORTED, "fp8 needs at least two hidden layers");
   if (d->precision == DDF_FP8_E4M3 && (d->width < 256 || L.k1 > 256))
     return fail(DDF_ERR_UNSUPPORTED, "fp8 needs width >= 256 and at most 128 padded input features");
   return DDF_OK;
@@ -220,7 +218,7 @@ int ddf_pack(const ddf_net_desc* d, const float* master, const float* act_scales
   if ((rc = check_ptr(master, "master"))) return rc;
   if ((rc = check_ptr(packed, "packed"))) return rc;
   if (d->precision == DDF_FP8_E4M3) {
-    if (!act_scales) return fail(DDF_ERR_INVALID_ARG, "fp8 packing needs act_scales");
+    if (!act_scales && d->n_hidden > 1) return fail(DDF_ERR_INVALID_ARG, "fp8 packing needs act_scales");
     for (int l = 0; l + 1 < d->n_hidden; ++l) {
       float s = act_scales[l];
       int e;
@@ -247,6 +245,20 @@ int ddf_query(const ddf_net_desc* d, const void* packed, const float* rays, int6
   a.in = rays; a.n = n; a.stride = n; a.mode = kModeQuery; a.out0 = t; a.out1 = xi;
   g_err[0] = 0;
   return hip_status(launch_forward(*d, a, n, (hipStream_t)stream), "ddf_query launch");
+}
+
+int ddf_query_hidden(const ddf_net_desc* d, const void* packed, const float* in, int64_t n, float* h,
+                     void* stream) {
+  int rc;
+  if ((rc = check_desc(d))) return rc;
+  if (n < 0 || n > (int64_t)INT32_MAX) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(packed, "packed")) || (rc = check_ptr(in, "rays")) || (rc = check_ptr(h, "h")))
+    return rc;
+  FwdArgs a = base_args(*d, packed);
+  a.in = in; a.n = n; a.stride = n; a.mode = kModeHidden; a.out0 = h;
+  g_err[0] = 0;
+  return hip_status(launch_forward(*d, a, n, (hipStream_t)stream), "ddf_query_hidden launch");
 }
 
 int sdf_eval(const ddf_net_desc* d, const void* packed, const float* points, int64_t n, float* sdf,

@@ -11,7 +11,8 @@ enum FwdMode {
   kModeSdf = 2,     // signed distance z_0 at points
   kModeTrace = 3,   // one sphere-tracing step over the active-ray list
   kModeCalib = 4,   // query that records max h_l of hidden layers 1..n-1 (FP8 scales)
-  kModeRecompute = 5  // training: rerun hidden layers from a kept activation, keeping theirs
+  kModeRecompute = 5,  // training: rerun hidden layers from a kept activation, keeping theirs
+  kModeHidden = 6      // the last hidden layer's float32 output h_n per ray, [n][width] in out0
 };
 
 struct FwdArgs {
@@ -22,7 +23,7 @@ struct FwdArgs {
   Layout lay;
   int n_in, n_freq, n_hidden, n_out;
   int mode;
-  float* out0;            // query: t; train: z_t; sdf: s
+  float* out0;            // query: t; train: z_t; sdf: s; hidden: h_n [n][width]
   float* out1;            // query: xi; train: z_xi
   // 0-based hidden layers this launch runs: [l_begin, l_end) (queries: all of them)
   int l_begin, l_end;

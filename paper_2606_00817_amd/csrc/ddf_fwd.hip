@@ -55,6 +55,10 @@ __device__ inline void epilogue_t(const FwdArgs& a,
         f32x4 y;
 #pragma unroll
         for (int i = 0; i < 4; ++i) y[i] = fmaxf(acc[rt][t][4 * q + i] + b4[i], 0.f);
+        if (MODE == kModeHidden && last) {
+          const int64_t g = ray0 + rt * 32 + (lane & 31);
+          if (g < n_act) *reinterpret_cast<f32x4*>(a.out0 + g * WIDTH + nb + 8 * q) = y;
+        }
         if (last) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
@@ -249,6 +253,8 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
       case kModeSdf:
         a.out0[g] = z0;
         break;
+      case kModeHidden:
+        break;
       default:
         trace_update(a, a.idx[g], z0);
         break;
@@ -271,6 +277,7 @@ static hipError_t launch_t(const FwdArgs& a, int64_t n_tiles, hipStream_t st) {
     case kModeRecompute:
       hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeRecompute, QW>), grid, bq, 0, st, a);
       break;
+    case kModeHidden: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeHidden, QW>), grid, bq, 0, st, a); break;
     default: hipLaunchKernelGGL((fwd_kernel<P, WIDTH, kModeTrace, QW>), grid, bq, 0, st, a); break;
   }
   return hipGetLastError();

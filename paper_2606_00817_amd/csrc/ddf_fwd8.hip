@@ -312,11 +312,16 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
             const f32x4 w1 = *reinterpret_cast<const f32x4*>(hw1 + nb + 8 * q);
 #pragma unroll
             for (int rt = 0; rt < kRT8; ++rt) {
+              f32x4 y;
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
-                const float y = fmaxf(fmaf(acc[rt][t][4 * q + i], dq, b4[i]), 0.f);
-                hp0[rt] = fmaf(w0[i], y, hp0[rt]);
-                hp1[rt] = fmaf(w1[i], y, hp1[rt]);
+                y[i] = fmaxf(fmaf(acc[rt][t][4 * q + i], dq, b4[i]), 0.f);
+                hp0[rt] = fmaf(w0[i], y[i], hp0[rt]);
+                hp1[rt] = fmaf(w1[i], y[i], hp1[rt]);
+              }
+              if (MODE == kModeHidden) {
+                const int64_t g = ray0 + rt * 32 + (el & 31);
+                if (g < n_act) *reinterpret_cast<f32x4*>(a.out0 + g * WIDTH + nb + 8 * q) = y;
               }
             }
           }
@@ -405,6 +410,7 @@ static hipError_t launch8_t(const FwdArgs& a, int64_t n_tiles, hipStream_t st) {
     case kModeQuery: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeQuery, QW>), grid, block, 0, st, a); break;
     case kModeSdf: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeSdf, QW>), grid, block, 0, st, a); break;
     case kModeTrace: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeTrace, QW>), grid, block, 0, st, a); break;
+    case kModeHidden: hipLaunchKernelGGL((fwd8_kernel<WIDTH, kModeHidden, QW>), grid, block, 0, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

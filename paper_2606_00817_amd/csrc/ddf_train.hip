@@ -879,6 +879,16 @@ int launch_adam_flat(float* p, float* m, float* v, const float* g, int64_t P, co
 
 int loss_scratch_floats() { return 8 * kLossBlocks; }
 
+// One kept activation slab ([rows / 8][width][8] in the operand type) as float32 [n][width].
+template <class E>
+__global__ void unpack_slab_kernel(const E* slab, int width, int64_t n, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * width) return;
+  const int64_t r = i / width;
+  const int c = (int)(i - r * width);
+  out[i] = (float)slab[((r >> 3) * width + c) * 8 + (r & 7)];
+}
+
 static int check_recompute(int recompute_every) {
   if (recompute_every < 0) return fail(DDF_ERR_INVALID_ARG, "recompute_every = %d must be >= 0", recompute_every);
   return DDF_OK;
@@ -910,6 +920,30 @@ int ddf_forward_train(const ddf_net_desc* d, const void* packed, const float* ra
   if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
   return run_forward_train(*d, packed, rays, n, z_t, d->n_out > 1 ? z_xi : z_t, w, static_cast<uint8_t*>(ws),
                            (hipStream_t)stream);
+}
+
+int ddf_train_kept_activation(const ddf_net_desc* d, int64_t n, int32_t recompute_every, const void* ws,
+                              size_t ws_bytes, int32_t layer, float* h, void* stream) {
+  int rc;
+  if ((rc = check_train_desc(d)) || (rc = check_recompute(recompute_every))) return rc;
+  if (n < 0 || n > (int64_t)INT32_MAX / 4) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (layer < 1 || layer > d->n_hidden)
+    return fail(DDF_ERR_INVALID_ARG, "layer %d outside 1..%d", layer, d->n_hidden);
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(ws, "ws")) || (rc = check_ptr(h, "h"))) return rc;
+  const TrainWs w = train_ws(*d, n, param_count_of(*d), recompute_every);
+  if ((int64_t)ws_bytes < w.total) return fail(DDF_ERR_WORKSPACE, "workspace %zu < %lld bytes", ws_bytes, (long long)w.total);
+  const TrainPtrs p = train_ptrs(*d, w, static_cast<uint8_t*>(const_cast<void*>(ws)));
+  if (!p.kept[layer])
+    return fail(DDF_ERR_INVALID_ARG, "H_%d is not kept with recompute_every = %d", layer, recompute_every);
+  hipStream_t st = (hipStream_t)stream;
+  const unsigned blocks = (unsigned)((n * d->width + 255) / 256);
+  if (d->precision == DDF_FP32)
+    unpack_slab_kernel<float><<<blocks, 256, 0, st>>>(reinterpret_cast<const float*>(p.h[layer]), d->width, n, h);
+  else
+    unpack_slab_kernel<__bf16><<<blocks, 256, 0, st>>>(reinterpret_cast<const __bf16*>(p.h[layer]), d->width, n, h);
+  g_err_clear();
+  return hip_status(hipGetLastError(), "kept activation unpack");
 }
 
 int ddf_backward(const ddf_net_desc* d, const void* packed, const float* rays, int64_t n, const float* grad_z_t,

@@ -74,6 +74,8 @@ SIGNATURES = {
     "sdf_sphere_trace": (ctypes.c_int, [_D, _P, _P, _I64, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                         _P, _P, _P, _P, _SZ, _P]),
     "sdf_eval": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P]),
+    "ddf_query_hidden": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P]),
+    "ddf_train_kept_activation": (ctypes.c_int, [_D, _I64, ctypes.c_int32, _P, _SZ, ctypes.c_int32, _P, _P]),
     "ddf_cast_targets": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P, _P, _P]),
     "ddf_scene_sdf": (ctypes.c_int, [_P, ctypes.c_int32, _P, _I64, _P, _P]),
     "ddf_shift_rays": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float, _I64, _P, _P, _P, _P]),
@@ -214,6 +216,16 @@ def query_split(desc, packed, rays, ws=None, t=None, xi=None):
     return t, xi
 
 
+def query_hidden(desc, precision, packed, inputs):
+    """The last hidden layer's float32 activations [n, width] for SoA inputs [n_in, n]."""
+    d = desc_c(desc, precision)
+    _dev(inputs, torch.float32, "inputs")
+    n = inputs.shape[1]
+    h = torch.empty((n, desc.width), dtype=torch.float32, device=inputs.device)
+    _check(lib().ddf_query_hidden(ctypes.byref(d), _ptr(packed), _ptr(inputs), n, _ptr(h), _stream()))
+    return h
+
+
 def sdf_eval(desc, precision, packed, points):
     d = desc_c(desc, precision)
     _dev(points, torch.float32, "points")
@@ -317,6 +329,15 @@ def forward_train(desc, precision, packed, rays, ws, recompute_every=0):
     _check(lib().ddf_forward_train(ctypes.byref(d), _ptr(packed), _ptr(rays), n, _ptr(zt), _ptr(zx),
                                    int(recompute_every), _ptr(ws), ws.numel(), _stream()))
     return zt, zx
+
+
+def train_kept_activation(desc, precision, n, ws, layer, recompute_every=0):
+    """H_layer as the training forward kept it in ws, float32 [n, width]."""
+    d = desc_c(desc, precision)
+    h = torch.empty((n, desc.width), dtype=torch.float32, device=ws.device)
+    _check(lib().ddf_train_kept_activation(ctypes.byref(d), int(n), int(recompute_every), _ptr(ws), ws.numel(),
+                                           int(layer), _ptr(h), _stream()))
+    return h
 
 
 def backward(desc, precision, packed, rays, grad_zt, grad_zx, ws, recompute_every=0):

@@ -92,3 +92,38 @@ def cuda():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return torch.device("cuda:0")
+
+
+def bf16_grad_fp32_accum(desc, params, gam, dz):
+    """The bf16 training gradient with the kernels' rounding points (as
+    oracle.ddf_oracle.mlp_backward_emulated_bf16) but every product summed in float32
+    (numpy's float32 matmul, another valid summation order).  Its distance from the exactly
+    accumulated emulation measures how far any float32-accumulating implementation may land
+    from it: a float32 difference that moves a value across a bf16 rounding boundary flips a
+    whole bf16 step, later layers carry it on, and a pre-activation near 0 flips its ReLU.
+    Also returns the post-ReLU activations of the float32-summed forward."""
+    f32 = np.float32
+
+    def mm(a, b):
+        return (np.asarray(a, dtype=f32) @ np.asarray(b, dtype=f32)).astype(np.float64)
+    L = O.layers(desc, params)
+    hi, lo = O.split_bf16(gam)
+    W1, b1 = L[0]
+    W1q = O.round_bf16(W1)
+    h = np.maximum(mm(hi, W1q.T) + mm(lo, W1q.T) + b1, 0.0)
+    hs = [h]
+    for W, b in L[1:-1]:
+        h = np.maximum(mm(O.round_bf16(h), O.round_bf16(W).T) + b, 0.0)
+        hs.append(h)
+    ins = [O.round_bf16(gam)] + [O.round_bf16(x) for x in hs]
+    dz = np.asarray(dz, dtype=np.float64)
+    grads = [None] * len(L)
+    Wh, _ = L[-1]
+    grads[-1] = (mm(dz.T, ins[-1]), dz.sum(axis=0))
+    da = O.round_bf16(mm(dz, Wh) * (hs[-1] > 0.0))
+    for l in range(len(L) - 2, -1, -1):
+        W, _ = L[l]
+        grads[l] = (mm(da.T, ins[l]), da.sum(axis=0))
+        if l > 0:
+            da = O.round_bf16(mm(da, O.round_bf16(W)) * (hs[l - 1] > 0.0))
+    return np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads]), hs

@@ -59,6 +59,82 @@ def test_hash_query_matches_oracle(desc, n, fused):
     assert dt.max() <= 2e-5 * max(1.0, np.abs(t64).max()) and dx.max() <= 5e-6
 
 
+def _coord_rounding_bound(desc, params, rays):
+    """Per-ray bound on |z(float32 grid coordinates) - z(exact)| (first two logits).
+
+    The kernel forms p = fl(fl(x + h) fl(0.5 / h)) and s = fl(p N): x + h (|x + h| <= 3) and
+    0.5 / h each carry one rounding, the product another, so |p_fp32 - p| <= 3 u and
+    |s_fp32 - s| <= 3 u N + u s <= 4 u N per axis (u = 2^-24); delta = 5 u N is used.  Over a
+    move of delta per axis the trilinear interpolant changes by at most delta times the largest
+    vertex-to-vertex feature difference along each axis, taken over the vertices of every cell
+    the move can reach (floor(s - delta) .. floor(s + delta) + 1), so a cell decided
+    differently near a face is covered too.  The feature bound is carried to the logits by the
+    MLP's Jacobian at the ray, |J| = |W_h diag(m_2) W_2 diag(m_1) W_1| (first order: the
+    masks m_l of the float64 forward; the changes are far too small to move a ReLU).  Returns
+    (bound [N, 2], share of rays with some coordinate within delta of a cell face)."""
+    table, mlp = H.split(desc, params)
+    x = np.asarray(rays, dtype=np.float64)[0:3].T
+    p = H.unit_coords(desc, x, "exact")
+    T = 1 << desc.log2_table
+    u = 2.0 ** -24
+    F = desc.n_feat
+    eps = np.zeros((len(x), desc.n_levels * F))
+    near = np.zeros(len(x), dtype=bool)
+    for l, (N, _, dense, off) in enumerate(H.levels(desc)):
+        s = p * N
+        dlt = 5 * u * N
+        lo = np.clip(np.floor(s - dlt), 0, N - 1).astype(np.int64)
+        hi = np.clip(np.floor(s + dlt), 0, N - 1).astype(np.int64) + 1
+        near |= np.any(lo + 1 != hi, axis=1) | np.any(np.abs(s - np.rint(s)) <= dlt, axis=1)
+        lip = np.zeros((len(x), F))
+        for a in range(3):
+            best = np.zeros((len(x), F))
+            # every edge along axis a between vertices lo..hi (at most 3 x 3 x 2 edges)
+            for i0 in range(2):
+                for i1 in range(3):
+                    for i2 in range(3):
+                        off3 = np.array([i0, i1, i2])
+                        v = lo + np.roll(off3, a)[None]
+                        ok = np.all(v + np.eye(3, dtype=np.int64)[a] <= hi, axis=1)
+                        va = v + np.eye(3, dtype=np.int64)[a]
+                        vi = off + H.vertex_index(N, dense, T, np.minimum(v, N))
+                        vj = off + H.vertex_index(N, dense, T, np.minimum(va, N))
+                        best = np.maximum(best, np.abs(table[vj] - table[vi]) * ok[:, None])
+            lip += best
+        eps[:, l * F:(l + 1) * F] = dlt * lip
+    (W1, _), (W2, _), (Wh, _) = mlp[0], mlp[1], mlp[2]
+    hs, _ = H.mlp_forward(mlp, H.encode(desc, params, rays, "exact"))
+    m1 = (hs[1] > 0).astype(np.float64)
+    m2 = (hs[2] > 0).astype(np.float64)
+    J = (Wh[None] * m2[:, None, :]) @ W2            # [N, 2, width]
+    J = (J * m1[:, None, :]) @ W1[:, :desc.n_levels * F]
+    return np.einsum('nok,nk->no', np.abs(J), eps), near.mean()
+
+
+@pytest.mark.parametrize("fused", [False, True], ids=["two-pass", "fused"])
+@pytest.mark.parametrize("desc", [I.HASH_SMALL, I.HASH_PAPER], ids=["6-level", "paper-16-level"])
+def test_hash_query_matches_exact_coordinates(desc, fused):
+    """Against the plain definition (float64 grid coordinates, coords="exact"): every ray
+    within the float32 arithmetic tolerance of the float32-coordinate gate plus the propagated
+    bound of the float32 coordinate rounding (_coord_rounding_bound)."""
+    dev = cuda()
+    params = _params(desc, 31)
+    sc = I.scene_mixed(256, 2)
+    rays = np.concatenate([I.free_rays(sc, 936, 32), _edge_rays(desc, 64, 33)], axis=1)
+    t, xi = ddf.hash_query(desc, _t(params, dev), _t(rays, dev), fused=fused)
+    torch.cuda.synchronize()
+    t = t.cpu().numpy().astype(np.float64); xi = xi.cpu().numpy().astype(np.float64)
+    t64, x64, _, _ = H.hash_query(desc, params, rays, coords="exact")
+    ez, near = _coord_rounding_bound(desc, params, rays)
+    tol_t = ez[:, 0] + 2e-5 * max(1.0, np.abs(t64).max())
+    tol_x = 0.25 * ez[:, 1] + 5e-6
+    dt = np.abs(t - t64); dx = np.abs(xi - x64)
+    print(f"hash query vs exact coordinates, {desc.n_levels} levels: max |dt| {dt.max():.2e} (bound median "
+          f"{np.median(tol_t):.2e}, max ratio {(dt / tol_t).max():.3f}); max |dxi| {dx.max():.2e} (ratio "
+          f"{(dx / tol_x).max():.3f}); {near:.4f} of rays within float32 rounding of a cell face")
+    assert np.all(dt <= tol_t) and np.all(dx <= tol_x)
+
+
 def test_hash_query_2p20_paper_field():
     """The benchmark's query (2^20 shadow rays, two-pass) on sampled rays; the fused path
     agrees to float32 rounding everywhere; a workspace one byte short is refused before any

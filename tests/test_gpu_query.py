@@ -110,16 +110,34 @@ def test_cast_targets_match_oracle():
     t = t.cpu().numpy(); hit = hit.cpu().numpy().astype(bool)
     tg, hg, _ = G.intersect_soa(sc, rays)
     agree = hit == hg
-    # a flip is only allowed at a grazing ray (float32 discriminant near zero)
-    assert agree.mean() > 0.998
+    # a flip is only allowed where float32 cannot decide: a primitive ahead of the origin whose
+    # discriminant B^2 - A C is within 64 float32 roundings of its terms (a grazing ray), or a
+    # root within 1e-4 of the origin (a start on a surface)
+    c, a, R = G._prim_arrays(sc)
+    o = rays[0:3].T.astype(np.float64); d = rays[3:6].T.astype(np.float64)
+    q = np.einsum('pji,npj->npi', R, o[:, None, :] - c[None]) / a[None]
+    e = np.einsum('pji,nj->npi', R, d) / a[None]
+    A = (e * e).sum(-1); B = (q * e).sum(-1); C = (q * q).sum(-1) - 1.0
+    disc = B * B - A * C
+    undecided = (np.abs(disc) <= 64 * 2.0 ** -24 * (B * B + np.abs(A * C))) & (-B / A > -1e-3)
+    sq = np.sqrt(np.maximum(disc, 0.0))
+    near0 = (disc >= 0) & (np.minimum(np.abs((-B - sq) / A), np.abs((-B + sq) / A)) < 1e-4)
+    explained = undecided.any(axis=1) | near0.any(axis=1)
+    print(f"cast: {(~agree).sum()} of {len(agree)} hit flags differ; {explained.mean():.4f} of rays are "
+          f"undecidable in float32")
+    assert np.all(explained[~agree]), np.nonzero(~agree & ~explained)[0][:10]
+    assert explained.mean() < 0.05
     both = hit & hg
     np.testing.assert_allclose(t[both], tg[both], rtol=2e-4, atol=2e-5)
     assert np.all(np.isinf(t[~hit]))
 
 
-def test_sphere_trace_planted_box_matches_oracle():
+@pytest.mark.parametrize("desc", [I.NetDesc(3, 10, 6, 256, 1), I.NET_SDF], ids=["6x256", "12x1024"])
+def test_sphere_trace_planted_box_matches_oracle(desc):
+    """fp32 sphere trace of a planted exact box SDF, also at the benchmark's SDF size
+    (3 -> 1024 x 12 -> 1): hit flags and step counts equal the float64 trace's on >= 98 % of
+    rays, t within 1e-4 there, every hit point on the box surface."""
     dev = cuda()
-    desc = I.NetDesc(3, 10, 6, 256, 1)
     half = [0.3, 0.5, 0.7]
     params = planted_box_sdf(desc, half, 7)
     rng = np.random.default_rng(3)
@@ -145,12 +163,12 @@ def test_sphere_trace_planted_box_matches_oracle():
     assert np.all(np.abs(box_sdf(p, half)) < 2e-4)
 
 
-def test_sphere_trace_bf16_planted_box():
+@pytest.mark.parametrize("desc", [I.NetDesc(3, 10, 6, 256, 1), I.NET_SDF], ids=["6x256", "12x1024"])
+def test_sphere_trace_bf16_planted_box(desc):
     """The bf16 trace (the same-precision baseline of the bf16 query): the same rays and
     settings as the fp32 trace, hit decisions agree with the float64 trace on most rays and
     every bf16 hit lies near the planted box surface (bf16 rounds the SDF to ~3 digits)."""
     dev = cuda()
-    desc = I.NetDesc(3, 10, 6, 256, 1)
     half = [0.3, 0.5, 0.7]
     params = planted_box_sdf(desc, half, 7)
     rng = np.random.default_rng(3)

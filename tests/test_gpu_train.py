@@ -8,7 +8,7 @@ from oracle import ddf_oracle as O
 from oracle import geometry as G
 from paper_2606_00817_amd import ddf
 from paper_2606_00817_amd import inputs as I
-from tests.helpers import cuda, kink_rays
+from tests.helpers import bf16_grad_fp32_accum, cuda, kink_rays
 
 pytestmark = pytest.mark.gpu
 
@@ -70,10 +70,13 @@ def test_bf16_backward_matches_emulated_oracle(n_hidden):
 
     With 3 layers the kernel reproduces the emulation closely.  With 12 layers a float32
     accumulation difference that moves a value across a bf16 rounding boundary perturbs
-    later pre-activations, a few ReLU masks flip, and each flip changes that ray's
-    gradient in every layer below; the kernel must still be much closer to the emulation
-    than the emulation is to float64 (bf16 itself flips ~0.3 % of the masks, cosine
-    ~0.985 against float64 at 12 x 1024; that is reported, and gated loosely)."""
+    later pre-activations and a few ReLU masks flip; each flip changes that ray's gradient
+    in every layer below.  So at 12 x 1024 the test compares ray by ray: the rays whose
+    ReLU masks (what the training forward kept, ddf_train_kept_activation) differ anywhere
+    from the emulation's carry no logit gradient on either side, and on every other ray the
+    gradients must agree to cosine >= 0.9999 and relative L2 <= 1e-2.  The unmasked
+    gradient must lie within 3x the distance at which another valid float32 summation order
+    (tests.helpers.bf16_grad_fp32_accum) lands from the exact emulation."""
     dev = cuda()
     desc = I.NetDesc(6, 10, n_hidden, 1024, 2)
     n = 640
@@ -104,9 +107,27 @@ def test_bf16_backward_matches_emulated_oracle(n_hidden):
     if n_hidden == 3:
         assert cos(got, em) >= 0.99995 and rel(got, em) <= 1e-2
         assert min(c for _, c in _per_layer_errors(desc, got, em)) >= 0.9995
-    else:
-        assert rel(got, em) <= 0.5 * rel(em, ref)
-        assert cos(got, ref) >= 0.95
+        return
+    hs_em, _ = O.mlp_forward_emulated(desc, params, gam, "bf16")
+    differ = np.zeros(n, dtype=bool)
+    for l in range(1, n_hidden + 1):
+        hk = ddf.train_kept_activation(desc, "bf16", n, ws, l).cpu().numpy()
+        differ |= ((hk > 0) != (hs_em[l - 1] > 0)).any(axis=1)
+    keep = (~differ).astype(np.float32)
+    gm = ddf.backward(desc, "bf16", packed, _t(rays, dev), _t(dzt * keep, dev), _t(dzx * keep, dev), ws)
+    torch.cuda.synchronize()
+    gm = gm.cpu().numpy().astype(np.float64)
+    em_m = O.mlp_backward_emulated_bf16(desc, params, gam, dz * keep[:, None])
+    sur, hs_sur = bf16_grad_fp32_accum(desc, params, gam, dz)
+    sur_differ = np.zeros(n, dtype=bool)
+    for l in range(n_hidden):
+        sur_differ |= ((hs_sur[l] > 0) != (hs_em[l] > 0)).any(axis=1)
+    print(f"  masked ({differ.sum()} of {n} rays with a ReLU mask unlike the emulation's; float32-summed "
+          f"emulation: {sur_differ.sum()}): cosine {cos(gm, em_m):.7f} rel L2 {rel(gm, em_m):.3g}; unmasked "
+          f"float32-summed emulation vs emulation rel L2 {rel(sur, em):.3g}")
+    assert cos(gm, em_m) >= 0.9999 and rel(gm, em_m) <= 1e-2
+    assert differ.mean() <= max(0.35, 2 * sur_differ.mean())
+    assert rel(got, em) <= 3 * rel(sur, em)
 
 
 def _train_inputs(desc, n, seed):
