@@ -1,21 +1,29 @@
 """Benchmark of the DDF hot path on one MI355X; prints ONE JSON line.
 
-Workload: the full-size query batch -- 2^20 shadow rays (surface points of a
-256-primitive sphere/ellipsoid scene, lifted along the normal, aimed at the
-point light at (0, 3, 0)) through the 12 x 1024 DDF (L = 10 encoding, 126
-features), random He-init weights (seed 0).  A timed step is one query of the
-whole batch (ray ingest, encoding, the fused layer chain and both heads) in
-the headline precision; the JSON line's `value` is the query throughput.
-Further legs run in the same invocation: the other query precisions on the same
-rays (each reduced precision's |dt| and flip rate against the fp32 query); the
-bf16 and fp8 queries at 1K, 10K and 100K rays; distillation training steps (65,536 rays through the 12 x 1024 net, and
-262,144 rays through the 16 x 1024 net with activations recomputed every 4
-layers, bf16 and fp32 each); and sphere tracing of a signed-distance MLP of the
-same size along the same rays (the paper's baseline); and the paper's own 52 MB hash-grid
-field, queried at 1K to 2^20 rays and trained on 16,384-ray batches; and that field,
-distilled by the paper's recipe on one object above a ground slab, answering a 512 x 512
-frame's shadow and AO rays (maps against exact casting).  The float64 oracle is timed on the
-host cores over a bounded sample of the same rays.
+Workload (the headline): the large mixed query batch -- 2^24 rays in one launch, 50 %
+shadow rays (surface points of a 256-primitive sphere/ellipsoid scene, lifted along the
+normal, aimed at the point light at (0, 3, 0)), 40 % ambient-occlusion rays (32
+cosine-weighted hemisphere rays per surface point) and 10 % one-bounce rays (uniform over
+the normal's hemisphere), in a fixed seeded interleave -- through the 16 x 1024 DDF (L = 10
+encoding, 126 features), random He-init weights (seed 0).  A timed step is one query of the
+whole batch (ray ingest, encoding, the fused layer chain and both heads) in the headline
+precision (bf16); the JSON line's `value` is its throughput.  Further legs run in the same
+invocation, each query leg with its own roofline and precision statistics:
+  * the same 2^24 rays in fp8 (e4m3, per-layer scales) and fp32;
+  * the ambient-occlusion batch: 512 x 512 surface points x 32 cosine rays (8,388,608 rays)
+    through the 12 x 1024 DDF in bf16, fp8 and fp32;
+  * 2^20 shadow rays through the 12 x 1024 DDF in fp32, bf16 and fp8, and sphere tracing of a
+    signed-distance MLP of the same size along the same rays (the paper's baseline);
+  * the bf16 and fp8 queries at 1K, 10K and 100K rays and the tiny 4 x 128 net;
+  * distillation training steps (65,536 rays through the 12 x 1024 net; 262,144 rays through
+    the 16 x 1024 net with activations recomputed every 4 layers; bf16 and fp32 each);
+  * the paper's own 52 MB hash-grid field, queried at 1K to 2^20 rays and trained on
+    16,384-ray batches, and that field distilled by the paper's recipe on one object above a
+    ground slab, answering a 512 x 512 frame's shadow and AO rays (maps against exact casting).
+Every reduced precision's max / mean |dt| and visibility flip rate is taken against the fp32
+query over all rays, and against the float64 oracle on every 16th ray of the 2^24-ray and
+8.4M-ray batches (computed on the host while the GPU legs run).  The float64 oracle is also
+timed alone on the host cores over a bounded sample of the headline rays (cpu_baseline).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision bf16]
 """
@@ -23,6 +31,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -30,11 +39,13 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
-FLOP_PER_RAY = {}          # algorithmic FLOPs per ray and net (no padding, no hi/lo split)
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp8": 5033.2}   # MI355X dense matrix peaks
-N_RAYS = 1 << 20
+N_HEAD = 1 << 24           # rays of the headline batch
+N_SHADOW = 1 << 20         # rays of the 12 x 1024 shadow batch
+AO_POINTS, AO_DIRS = 512 * 512, 32
+SUBSET = 16                # the float64 oracle answers every 16th ray of the large batches
 
-# HBM traffic of one launch of the timed query kernel, from two rocprofv3 counter passes over
+# HBM traffic of one launch of the headline query kernel, from two rocprofv3 counter passes over
 # this workload (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same
 # counter reads for a 1 GiB device copy in the same run (FETCH_SIZE reads 524,306 KiB for
 # 1,048,576 KiB fetched: x2; WRITE_SIZE reads 1,048,576 KiB: x1).  The figures hold for the
@@ -42,16 +53,15 @@ N_RAYS = 1 << 20
 # files the bench reports null until the counters are taken again.
 COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 TRAFFIC_KIB = {
-    "bf16": {"FETCH_SIZE": 5925033, "WRITE_SIZE": 8192,
-             "sha256": "439fb400e43d5295381397c33c0c19e59a467b2b043bf0249a40ecff96a16f51"},
-    "fp8": {"FETCH_SIZE": 1552400, "WRITE_SIZE": 61420,
-            "sha256": "7ff934cdecf1833492721fd4307502ddf9399290488ff3a8c1836dfd30e63c36"},
+    "bf16": {"FETCH_SIZE": 128417962, "WRITE_SIZE": 131072,
+             "sha256": "70c71fc84c825b2f7cf939a94d013ab7b81714e4b0200fcffedf2b977059d03d"},
 }
 KERNEL_SOURCES = {
     "fp32": ["ddf_fwd.hip", "ddf_chain.h", "ddf_fwd.h", "ddf_internal.h"],
     "bf16": ["ddf_fwd.hip", "ddf_chain.h", "ddf_fwd.h", "ddf_internal.h"],
     "fp8": ["ddf_fwd8.hip", "ddf_fwd.h", "ddf_internal.h"],
 }
+KERNEL_NAME = {"fp32": "fwd_kernel (fp32)", "bf16": "fwd_kernel (bf16)", "fp8": "fwd8_kernel"}
 
 
 def kernel_source_hash(prec):
@@ -95,28 +105,52 @@ class KernelTimer:
         return e0.elapsed_time(e1) / reps
 
 
-def cpu_oracle_baseline(desc, params, rays_np, answers, budget_s=12.0):
-    """The float64 oracle on a bounded sample of the same rays (rank 0, N = 1); its answers
-    also give each precision's |dt| and flip rate against float64 on that sample."""
-    from oracle import ddf_oracle as O
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+        return max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
     except Exception:
-        threads = os.cpu_count()
-    probe = 1024
+        return os.cpu_count()
+
+
+def cpu_oracle_baseline(desc, params, rays_np, budget_s=12.0):
+    """The float64 oracle timed alone on the host cores over a bounded sample of the headline
+    rays (rank 0, N = 1): about budget_s seconds of work."""
+    from oracle import ddf_oracle as O
+    probe = 512
     t0 = time.perf_counter()
     O.ddf_query(desc, params, rays_np[:, :probe])
     dt = time.perf_counter() - t0
     n = int(min(rays_np.shape[1], max(probe, probe * budget_s / max(dt, 1e-6))))
     n = max(probe, n // probe * probe)
     t0 = time.perf_counter()
-    t64, x64, _, _ = O.ddf_query(desc, params, rays_np[:, :n])
+    O.ddf_query(desc, params, rays_np[:, :n])
     dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "rays/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {n} of the {rays_np.shape[1]} shadow rays, float64 numpy forward "
-                      f"({dt:.1f} s)",
-            "precision_vs_float64": {p: dt_stats(t64, x64, t[:n], xi[:n]) for p, (t, xi) in answers.items()}}
+    return {"value": n / dt, "unit": "rays/s", "cores": int(blas_threads()), "kind": "oracle",
+            "sample": f"first {n} of the {rays_np.shape[1]} headline rays (mixed shadow/AO/GI, "
+                      f"{desc.width}x{desc.n_hidden} net), float64 numpy forward, {dt:.1f} s"}
+
+
+class OracleSubsets(threading.Thread):
+    """The float64 oracle on every SUBSET-th ray of the large batches, on the host while the GPU
+    legs run (numpy's BLAS threads do the work; the GIL is released inside them)."""
+
+    def __init__(self):
+        super().__init__(daemon=True)
+        self.jobs, self.results, self.error = [], {}, None
+
+    def add(self, name, desc, params, rays_np):
+        self.jobs.append((name, desc, params, np.ascontiguousarray(rays_np[:, ::SUBSET])))
+
+    def run(self):
+        try:
+            from oracle import ddf_oracle as O
+            for name, desc, params, r in self.jobs:
+                t0 = time.perf_counter()
+                t64, x64, _, _ = O.ddf_query(desc, params, r)
+                self.results[name] = (t64, x64, r.shape[1], time.perf_counter() - t0)
+        except Exception as e:   # reported in the JSON line, never hidden
+            self.error = repr(e)
 
 
 def dt_stats(t_ref, x_ref, t, xi):
@@ -135,14 +169,60 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+class QueryLeg:
+    """One query batch on one net: every precision timed on the same rays, with its roofline."""
+
+    def __init__(self, torch, ddf, dev, timer, desc, params_np, rays_np, calib):
+        self.torch, self.ddf, self.dev, self.timer = torch, ddf, dev, timer
+        self.desc, self.n = desc, rays_np.shape[1]
+        self.rays = torch.from_numpy(rays_np).to(dev)
+        self.master = torch.from_numpy(params_np).to(dev)
+        self.packed32 = ddf.pack(desc, "fp32", self.master)
+        self.scales = ddf.fp8_act_scales(desc, self.packed32, calib)
+        self.fpr = flop_per_ray(desc)
+        self.t = torch.empty(self.n, dtype=torch.float32, device=dev)
+        self.xi = torch.empty(self.n, dtype=torch.float32, device=dev)
+        self.answers = {}
+
+    def packed(self, prec):
+        if prec == "fp32":
+            return self.packed32
+        return self.ddf.pack(self.desc, prec, self.master, act_scales=self.scales if prec == "fp8" else None)
+
+    def run(self, prec, steps, warmup):
+        ddf, torch = self.ddf, self.torch
+        pk = self.packed(prec)
+        dc = ddf.desc_c(self.desc, prec)
+        for _ in range(warmup):
+            ddf.query_into(dc, pk, self.rays, self.t, self.xi)
+        torch.cuda.synchronize()
+        ms = self.timer.time(lambda: ddf.query_into(dc, pk, self.rays, self.t, self.xi), steps)
+        torch.cuda.synchronize()
+        self.answers[prec] = (self.t.cpu().numpy(), self.xi.cpu().numpy())
+        tf = self.fpr * self.n / (ms * 1e-3) / 1e12
+        return {"ms": ms, "rays_per_s": self.n / (ms * 1e-3), "launches_timed": steps,
+                "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                             "frac": tf / PEAK_TFLOPS[prec], "kernel": KERNEL_NAME[prec],
+                             "flop_per_launch": self.fpr * self.n}}
+
+    def vs_fp32(self, prec):
+        t32, x32 = self.answers["fp32"]
+        return dt_stats(t32, x32, *self.answers[prec])
+
+    def vs_float64(self, prec, t64, x64):
+        t, xi = self.answers[prec]
+        return dt_stats(t64, x64, t[::SUBSET], xi[::SUBSET])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--legs", default="precisions,sparse,train,train_large,trace,hash,shade,cpu",
-                    help="comma list of extra legs: precisions, sparse, train, train_large, trace, hash, shade, "
+    ap.add_argument("--legs", default="precisions,ao,shadow,sparse,train,train_large,trace,hash,shade,oracle,cpu",
+                    help="comma list of extra legs: precisions (fp8/fp32 of the headline rays), ao, shadow, "
+                         "sparse, train, train_large, trace (needs shadow), hash, shade, oracle (float64 subsets), "
                          "cpu, copy")
     ap.add_argument("--shade-steps", type=int, default=30000,
                     help="recipe steps of the hash-grid field trained for the shade leg")
@@ -161,32 +241,22 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    desc = I.NET_FULL
-    scene = I.scene_mixed(256, 2)
-    rays_np = I.shadow_rays(scene, N_RAYS, 12)
-    params_np = I.he_init(desc, 0)
-    rays = torch.from_numpy(rays_np).to(dev)
-    master = torch.from_numpy(params_np).to(dev)
     timer = KernelTimer(torch)
-    fpr = flop_per_ray(desc)
-
-    # FP8 activation scales from a calibration batch (free-space rays, seed 21)
-    calib = torch.from_numpy(I.free_rays(scene, 4096, 21)).to(dev)
-    packed32 = ddf.pack(desc, "fp32", master)
-    scales = ddf.fp8_act_scales(desc, packed32, calib)
-
-    def run_query(prec, steps, warmup):
-        packed = packed32 if prec == "fp32" else ddf.pack(desc, prec, master,
-                                                          act_scales=scales if prec == "fp8" else None)
-        dc = ddf.desc_c(desc, prec)
-        t = torch.empty(N_RAYS, dtype=torch.float32, device=dev)
-        xi = torch.empty(N_RAYS, dtype=torch.float32, device=dev)
-        for _ in range(warmup):
-            ddf.query_into(dc, packed, rays, t, xi)
-        torch.cuda.synchronize()
-        ms = timer.time(lambda: ddf.query_into(dc, packed, rays, t, xi), steps)
-        torch.cuda.synchronize()
-        return ms, t.cpu().numpy(), xi.cpu().numpy()
+    scene = I.scene_mixed(256, 2)
+    calib = torch.from_numpy(I.free_rays(scene, 4096, 21)).to(dev)   # FP8 calibration batch
+    t_in = time.perf_counter()
+    head_np = I.mixed_rays(scene, N_HEAD, 15)
+    head_params = I.he_init(I.NET_LARGE, 0)
+    oracle = OracleSubsets()
+    if "oracle" in legs:
+        oracle.add("mixed", I.NET_LARGE, head_params, head_np)
+    ao_np = I.ao_rays(scene, AO_POINTS, AO_DIRS, 13) if "ao" in legs else None
+    full_params = I.he_init(I.NET_FULL, 0)
+    if ao_np is not None and "oracle" in legs:
+        oracle.add("ao", I.NET_FULL, full_params, ao_np)
+    if oracle.jobs:
+        oracle.start()
+    progress(f"inputs drawn ({time.perf_counter() - t_in:.1f} s)")
 
     if "copy" in legs:
         # a plain copy kernel of known size (1 GiB read + 1 GiB written): the reference that
@@ -197,112 +267,147 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # ---- the timed region: K steps of the headline-precision query
+    # ---- the timed region: K steps of the headline-precision query of the 2^24 mixed rays
+    head = QueryLeg(torch, ddf, dev, timer, I.NET_LARGE, head_params, head_np, calib)
     prec = args.precision
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
-    ms, t_h, xi_h = run_query(prec, args.steps, args.warmup)
+    hl = head.run(prec, args.steps, args.warmup)
     wall = time.perf_counter() - wall0
-    value = N_RAYS / (ms * 1e-3)
-    achieved = fpr * N_RAYS / (ms * 1e-3) / 1e12
+    ms = hl["ms"]
+    roof = dict(hl["roofline"])
+    roof["traffic"] = traffic_bytes(prec)
+    roof["kernel"] = f"{KERNEL_NAME[prec]}, one launch per step"
     out = {
         "metric": "DDF rays/sec + MFMA util, BF16/FP8 vs FP32 at stated |dt|; train rays/sec",
-        "value": value, "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "value": N_HEAD / (ms * 1e-3), "unit": "rays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": prec, "data": "synthetic (seeded analytic scene, He-init weights)",
-        "config": {"workload": "2^20 shadow rays, 256-primitive scene, 12x1024 DDF (L=10, 126 features)",
-                   "rays": N_RAYS, "net": "126-1024x12-2", "precision": prec},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS[prec], "traffic": traffic_bytes(prec),
-                     "kernel": f"fwd_kernel ({prec}), one launch per step",
-                     "flop_per_launch": fpr * N_RAYS},
+        "config": {"workload": "2^24 mixed rays in one launch (50% shadow, 40% AO x32 per point, 10% one-bounce "
+                               "GI), 256-primitive scene, 16x1024 DDF (L=10, 126 features)",
+                   "rays": N_HEAD, "net": "126-1024x16-2", "precision": prec},
+        "roofline": roof,
     }
-    answers = {prec: (t_h, xi_h)}
-    others = ("fp32", "bf16", "fp8") if "precisions" in legs else ("fp32",)
+    progress(f"headline done ({prec} {ms:.2f} ms/step)")
     res = {}
-    for p in others:
-        if p == prec:
-            continue
-        steps = 3 if p == "fp32" else max(3, args.steps // 2)
-        msp, tp, xp = run_query(p, steps, 1)
-        answers[p] = (tp, xp)
-        tf = fpr * N_RAYS / (msp * 1e-3) / 1e12
-        res[p] = {"rays_per_s": N_RAYS / (msp * 1e-3), "ms": msp, "tflops": tf, "frac": tf / PEAK_TFLOPS[p]}
-    # the precision cost: every reduced-precision answer against the fp32 query, all 2^20 rays
-    t32, x32 = answers["fp32"]
-    out["precision_stats"] = {prec: dt_stats(t32, x32, t_h, xi_h) if prec != "fp32" else None}
-    for p in res:
-        if p != "fp32":
-            res[p].update(dt_stats(t32, x32, *answers[p]))
     if "precisions" in legs:
-        out["precisions"] = res
+        for p in ("fp32", "bf16", "fp8"):
+            if p != prec:
+                res[p] = head.run(p, 3 if p == "fp32" else max(3, args.steps // 2), 1)
+    if "fp32" in head.answers:
+        for p in head.answers:
+            if p == "fp32":
+                continue
+            st = head.vs_fp32(p)
+            if p == prec:
+                out["precision_stats"] = {"vs_fp32_all_rays": {p: st}}
+            else:
+                res[p]["vs_fp32_all_rays"] = st
+    out["mixed_2p24_16x1024"] = res
+    progress("headline precisions done")
 
-    progress(f"queries done ({prec} {ms:.2f} ms/step)")
-    if "sparse" in legs:
-        # the sparse-query regime (the paper's 1K-100K ray counts): per-call time of the dense
-        # query in each reduced precision on the first n rays, and of the bf16 small-batch path
-        sp = {}
+    ao = None
+    if ao_np is not None:
+        ao = QueryLeg(torch, ddf, dev, timer, I.NET_FULL, full_params, ao_np, calib)
+        r = {p: ao.run(p, 3 if p == "fp32" else 10, 1) for p in ("bf16", "fp8", "fp32")}
         for p in ("bf16", "fp8"):
-            pk = ddf.pack(desc, p, master, act_scales=scales if p == "fp8" else None)
-            dc = ddf.desc_c(desc, p)
-            row = {}
-            for n in (1000, 10000, 100000):
-                r = rays[:, :n].contiguous()
-                tq = torch.empty(n, dtype=torch.float32, device=dev)
-                xq = torch.empty(n, dtype=torch.float32, device=dev)
-                for _ in range(3):
-                    ddf.query_into(dc, pk, r, tq, xq)
-                torch.cuda.synchronize()
-                msn = timer.time(lambda: ddf.query_into(dc, pk, r, tq, xq), 20)
-                row[str(n)] = {"ms": msn, "rays_per_s": n / (msn * 1e-3), "us_per_ray": msn * 1e3 / n}
-                if p == "bf16":
-                    # the small-batch path: one launch per layer, neurons split over workgroups
-                    wsq = torch.empty(ddf.query_split_workspace_bytes(desc, n), dtype=torch.uint8, device=dev)
-                    for _ in range(3):
-                        ddf.query_split(desc, pk, r, ws=wsq, t=tq, xi=xq)
-                    torch.cuda.synchronize()
-                    msn = timer.time(lambda: ddf.query_split(desc, pk, r, ws=wsq, t=tq, xi=xq), 20)
-                    row[str(n)]["split"] = {"ms": msn, "rays_per_s": n / (msn * 1e-3), "us_per_ray": msn * 1e3 / n}
-            sp[p] = row
-        # the tiny configuration: 4,096 free rays through the 4 x 128 net in fp32 (launch-bound)
-        dt_ = I.NET_TINY
-        pk = ddf.pack(dt_, "fp32", torch.from_numpy(I.he_init(dt_, 0)).to(dev))
-        rt_ = torch.from_numpy(I.free_rays(I.scene_spheres(16, 1), 4096, 11)).to(dev)
-        tq = torch.empty(4096, dtype=torch.float32, device=dev)
-        xq = torch.empty(4096, dtype=torch.float32, device=dev)
-        dct = ddf.desc_c(dt_, "fp32")
-        for _ in range(3):
-            ddf.query_into(dct, pk, rt_, tq, xq)
-        torch.cuda.synchronize()
-        mst = timer.time(lambda: ddf.query_into(dct, pk, rt_, tq, xq), 50)
-        sp["tiny_4x128_fp32_4096_rays"] = {"us_per_launch": mst * 1e3, "rays_per_s": 4096 / (mst * 1e-3)}
-        out["sparse_queries"] = sp
+            r[p]["vs_fp32_all_rays"] = ao.vs_fp32(p)
+        out["ao_8p4M_12x1024"] = r
+        progress("ao leg done")
+        del ao_np
+
+    shadow = None
+    if "shadow" in legs:
+        shadow_np = I.shadow_rays(scene, N_SHADOW, 12)
+        shadow = QueryLeg(torch, ddf, dev, timer, I.NET_FULL, full_params, shadow_np, calib)
+        r = {p: shadow.run(p, 5 if p == "fp32" else 20, 2) for p in ("fp32", "bf16", "fp8")}
+        for p in ("bf16", "fp8"):
+            r[p]["vs_fp32_all_rays"] = shadow.vs_fp32(p)
+        out["shadow_2p20_12x1024"] = r
+        progress("shadow leg done")
+
+    if "sparse" in legs and shadow is not None:
+        out["sparse_queries"] = sparse_leg(torch, ddf, I, dev, timer, shadow)
         progress("sparse leg done")
     if "train" in legs:
         out["train"] = train_leg(torch, ddf, I, dev, timer, args.steps)
         progress("train leg done")
-
     if "train_large" in legs:
         out["train_large"] = train_leg(torch, ddf, I, dev, timer, 4, batch=1 << 18, desc=I.NET_LARGE,
                                        recompute_every=4, seed=1300, lr=3e-4)
         progress("train_large leg done")
-
-    if "trace" in legs:
-        out["sphere_trace"] = trace_leg(torch, ddf, I, dev, rays, timer, out, scene, args.sdf_fit_steps)
+    if "trace" in legs and shadow is not None:
+        out["sphere_trace"] = trace_leg(torch, ddf, I, dev, shadow.rays, timer, out["shadow_2p20_12x1024"], scene,
+                                        args.sdf_fit_steps)
         progress("trace leg done")
-
     if "hash" in legs:
-        out["hash_grid"] = hash_leg(torch, ddf, I, dev, rays, timer, args.steps)
+        rays_h = shadow.rays if shadow is not None else torch.from_numpy(I.shadow_rays(scene, N_SHADOW, 12)).to(dev)
+        out["hash_grid"] = hash_leg(torch, ddf, I, dev, rays_h, timer, args.steps)
         progress("hash leg done")
-
     if "shade" in legs:
         out["shading"] = shade_leg(torch, ddf, I, dev, timer, args.shade_steps)
         progress("shade leg done")
 
+    if oracle.jobs:
+        oracle.join()
+        if oracle.error:
+            out["oracle_subsets_error"] = oracle.error
+        for name, leg, key in (("mixed", head, "mixed_2p24_16x1024"), ("ao", ao, "ao_8p4M_12x1024")):
+            if name not in oracle.results or leg is None:
+                continue
+            t64, x64, n64, secs = oracle.results[name]
+            sub = {"rays": n64, "every": SUBSET, "oracle_s": secs}
+            for p in leg.answers:
+                sub[p] = leg.vs_float64(p, t64, x64)
+            out.setdefault(key, {})["vs_float64_subset"] = sub
+            if name == "mixed":
+                out.setdefault("precision_stats", {})["vs_float64_subset"] = sub
+        progress("oracle subsets done")
     if "cpu" in legs:
-        out["cpu_baseline"] = cpu_oracle_baseline(desc, params_np, rays_np, answers)
+        out["cpu_baseline"] = cpu_oracle_baseline(I.NET_LARGE, head_params, head_np)
     out["wall_s_timed"] = wall
     print(json.dumps(out))
+
+
+def sparse_leg(torch, ddf, I, dev, timer, shadow):
+    """The sparse-query regime (the paper's 1K-100K ray counts): per-call time of the dense
+    12 x 1024 query in each reduced precision on the first n shadow rays, and of the bf16
+    small-batch path; and the tiny configuration (4,096 free rays, 4 x 128 net, fp32)."""
+    sp = {}
+    desc = shadow.desc
+    for p in ("bf16", "fp8"):
+        pk = shadow.packed(p)
+        dc = ddf.desc_c(desc, p)
+        row = {}
+        for n in (1000, 10000, 100000):
+            r = shadow.rays[:, :n].contiguous()
+            tq = torch.empty(n, dtype=torch.float32, device=dev)
+            xq = torch.empty(n, dtype=torch.float32, device=dev)
+            for _ in range(3):
+                ddf.query_into(dc, pk, r, tq, xq)
+            torch.cuda.synchronize()
+            msn = timer.time(lambda: ddf.query_into(dc, pk, r, tq, xq), 20)
+            row[str(n)] = {"ms": msn, "rays_per_s": n / (msn * 1e-3), "us_per_ray": msn * 1e3 / n}
+            if p == "bf16":
+                wsq = torch.empty(ddf.query_split_workspace_bytes(desc, n), dtype=torch.uint8, device=dev)
+                for _ in range(3):
+                    ddf.query_split(desc, pk, r, ws=wsq, t=tq, xi=xq)
+                torch.cuda.synchronize()
+                msn = timer.time(lambda: ddf.query_split(desc, pk, r, ws=wsq, t=tq, xi=xq), 20)
+                row[str(n)]["split"] = {"ms": msn, "rays_per_s": n / (msn * 1e-3), "us_per_ray": msn * 1e3 / n}
+        sp[p] = row
+    dt_ = I.NET_TINY
+    pk = ddf.pack(dt_, "fp32", torch.from_numpy(I.he_init(dt_, 0)).to(dev))
+    rt_ = torch.from_numpy(I.free_rays(I.scene_spheres(16, 1), 4096, 11)).to(dev)
+    tq = torch.empty(4096, dtype=torch.float32, device=dev)
+    xq = torch.empty(4096, dtype=torch.float32, device=dev)
+    dct = ddf.desc_c(dt_, "fp32")
+    for _ in range(3):
+        ddf.query_into(dct, pk, rt_, tq, xq)
+    torch.cuda.synchronize()
+    mst = timer.time(lambda: ddf.query_into(dct, pk, rt_, tq, xq), 50)
+    sp["tiny_4x128_fp32_4096_rays"] = {"us_per_launch": mst * 1e3, "rays_per_s": 4096 / (mst * 1e-3)}
+    return sp
 
 
 def train_flop_per_ray(desc):
@@ -562,7 +667,7 @@ def trace_leg(torch, ddf, I, dev, rays, timer, out, scene, fit_steps=400):
     prims = torch.from_numpy(ddf.scene_prims(scene)).to(dev)
     tg, hg = ddf.cast_targets(prims, rays)
     st = steps.float()
-    prec = out.get("precisions", {})
+    prec = out   # the shadow leg's query timings on the same rays, per precision
     hist = torch.bincount(steps.long().clamp(0, 128), minlength=129).cpu().numpy()
     edges = [1, 2, 4, 8, 16, 32, 64, 128, 129]
     res = {"sdf": "12x1024 SDF MLP (L=10, 63 features) fitted to the scene's distance bound",
@@ -575,7 +680,7 @@ def trace_leg(torch, ddf, I, dev, rays, timer, out, scene, fit_steps=400):
            "hit_rate": float(hit.float().mean().item()),
            "hit_agreement_vs_exact_cast": float((hit == hg).float().mean().item())}
     for p in ("fp32", "bf16", "fp8"):
-        msp = prec.get(p, {}).get("ms") if p != out["dtype"] else out["ms_per_step"]
+        msp = prec.get(p, {}).get("ms")
         if msp:
             res[f"speedup_vs_ddf_{p}"] = ms / msp
     # the bf16 trace (one timed run)
@@ -585,7 +690,7 @@ def trace_leg(torch, ddf, I, dev, rays, timer, out, scene, fit_steps=400):
     res["bf16"] = {"ms": ms16, "rays_per_s": n / (ms16 * 1e-3), "mean_steps": float(s16.mean().item()),
                    "unconverged_fraction": float((steps16 >= 128).float().mean().item()),
                    "hit_agreement_vs_exact_cast": float((hit16 == hg).float().mean().item())}
-    msb = prec.get("bf16", {}).get("ms") if out["dtype"] != "bf16" else out["ms_per_step"]
+    msb = prec.get("bf16", {}).get("ms")
     if msb:
         res["bf16"]["speedup_vs_ddf_bf16"] = ms16 / msb
     return res
