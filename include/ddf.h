@@ -318,6 +318,19 @@ size_t ddf_hash_query_workspace_bytes(const ddf_hash_desc* desc, int64_t n);
 int ddf_hash_query(const ddf_hash_desc* desc, const float* params, const float* rays, int64_t n,
                    float* t, float* xi, void* ws, size_t ws_bytes, void* stream);
 
+/* The two-pass query without a caller workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same kernels and results as ddf_hash_query with ws, bit for bit, with the lookups staged in
+ * a 64 MiB array inside the library (held by every GPU the library runs on until the process
+ * ends).  The call allocates nothing.  n <= ddf_hash_query_static_max_rays() (524,288), else
+ * DDF_ERR_INVALID_ARG with nothing written; other arguments as for ddf_hash_query.  Every
+ * call on a GPU uses that GPU's one array, fully overwritten before it is read: calls that
+ * overlap on one GPU (other streams, other threads) race and must be serialised by the
+ * caller. */
+int64_t ddf_hash_query_static_max_rays(void);
+int ddf_hash_query_static(const ddf_hash_desc* desc, const float* params, const float* rays, int64_t n,
+                          float* t, float* xi, void* stream);
+
 /* The reduced-precision query (Sec. III-C: inference runs in reduced precision): a float16
  * copy of the table, round to nearest even, [entries][2] (ddf_hash_table_f16_bytes bytes,
  * device), made after each change to params; the lookups read it (half the bytes and cache

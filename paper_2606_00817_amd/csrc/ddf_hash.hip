@@ -16,6 +16,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include <hip/hip_fp16.h>
 
@@ -1007,6 +1008,39 @@ int run_hash_scatter(const HashArgs& a, const float* dg, hipStream_t st) {
 
 }  // namespace ddf
 
+namespace ddf {
+
+// The allocation-free two-pass query's workspace: one array in the library's code object,
+// [kHGroups][kHashStaticRays][4] floats (64 MiB), which every GPU the library runs on holds until
+// the process ends.  Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): each device's address comes from hipGetSymbolAddress, taken
+// once per device with that device current.
+constexpr int64_t kHashStaticRays = 1 << 19;
+static __device__ __align__(256) float4 hash_scratch[kHGroups * kHashStaticRays];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];   // per device ordinal; null until first looked up
+
+// The device address of hash_scratch on the current device, looked up on the first call there.
+static int hash_scratch_ptr(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_status(e, "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(DDF_ERR_UNSUPPORTED, "device ordinal %d beyond 63", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(hash_scratch));
+    if (e != hipSuccess) return hip_status(e, "hipGetSymbolAddress(hash_scratch)");
+    if (!p) return fail(DDF_ERR_HIP, "hipGetSymbolAddress(hash_scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DDF_OK;
+}
+
+}  // namespace ddf
+
 using namespace ddf;
 
 extern "C" {
@@ -1049,6 +1083,26 @@ int ddf_hash_query(const ddf_hash_desc* d, const float* params, const float* ray
     if (ws_bytes < (size_t)n * kHGroups * 16)
       return fail(DDF_ERR_INVALID_ARG, "workspace %zu bytes < %zu", ws_bytes, (size_t)n * kHGroups * 16);
   }
+  g_err_clear();
+  return run_hash_forward(make_hash_layout(*d), params, rays, n, 0, t, xi, static_cast<float*>(ws),
+                          (hipStream_t)stream);
+}
+
+int64_t ddf_hash_query_static_max_rays(void) { return kHashStaticRays; }
+
+int ddf_hash_query_static(const ddf_hash_desc* d, const float* params, const float* rays, int64_t n, float* t,
+                          float* xi, void* stream) {
+  int rc;
+  if ((rc = check_hash_desc(d))) return rc;
+  if (n < 0 || n > kHashStaticRays)
+    return fail(DDF_ERR_INVALID_ARG, "n = %lld outside 0..%lld (the static workspace's capacity)", (long long)n,
+                (long long)kHashStaticRays);
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(params, "params")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(t, "t")) ||
+      (rc = check_ptr(xi, "xi")))
+    return rc;
+  void* ws = nullptr;
+  if ((rc = hash_scratch_ptr(&ws))) return rc;
   g_err_clear();
   return run_hash_forward(make_hash_layout(*d), params, rays, n, 0, t, xi, static_cast<float*>(ws),
                           (hipStream_t)stream);

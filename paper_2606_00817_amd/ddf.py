@@ -85,6 +85,8 @@ SIGNATURES = {
                                       ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int32)]),
     "ddf_hash_query_workspace_bytes": (_SZ, [ctypes.POINTER(HashDescC), _I64]),
     "ddf_hash_query": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _I64, _P, _P, _P, _SZ, _P]),
+    "ddf_hash_query_static_max_rays": (_I64, []),
+    "ddf_hash_query_static": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _I64, _P, _P, _P]),
     "ddf_hash_table_f16_bytes": (_SZ, [ctypes.POINTER(HashDescC)]),
     "ddf_hash_table_to_f16": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _P]),
     "ddf_hash_query_f16": (ctypes.c_int, [ctypes.POINTER(HashDescC), _P, _P, _P, _I64, _P, _P, _P, _SZ, _P]),
@@ -462,6 +464,23 @@ def hash_query(desc, params: torch.Tensor, rays: torch.Tensor, ws: torch.Tensor 
         ws = torch.empty(hash_query_workspace_bytes(desc, n), dtype=torch.uint8, device=rays.device)
     wp, wb = (None, 0) if fused or ws is None else (_ptr(ws), ws.numel() * ws.element_size())
     _check(lib().ddf_hash_query(ctypes.byref(d), _ptr(params), _ptr(rays), n, _ptr(t), _ptr(xi), wp, wb, _stream()))
+    return t, xi
+
+
+def hash_query_static_max_rays() -> int:
+    return int(lib().ddf_hash_query_static_max_rays())
+
+
+def hash_query_static(desc, params: torch.Tensor, rays: torch.Tensor, t: torch.Tensor, xi: torch.Tensor):
+    """The two-pass query with the library's own static workspace (allocates nothing: the
+    caller passes the outputs)."""
+    _dev(params, torch.float32, "params")
+    _dev(rays, torch.float32, "rays")
+    _dev(t, torch.float32, "t")
+    _dev(xi, torch.float32, "xi")
+    d = hash_desc_c(desc)
+    _check(lib().ddf_hash_query_static(ctypes.byref(d), _ptr(params), _ptr(rays), rays.shape[1], _ptr(t), _ptr(xi),
+                                       _stream()))
     return t, xi
 
 
