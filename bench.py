@@ -545,12 +545,14 @@ def hash_leg(torch, ddf, I, dev, rays, timer, steps):
 
 
 def shade_leg(torch, ddf, I, dev, timer, steps):
-    """The renderer's use of the field (shadows and AO, the paper's Table VI analogue): the
-    paper's hash-grid field distilled by its recipe (`steps` steps of 16,384 fresh GPU-sampled
-    rays, 30 % self-consistency points, cosine lr from 3e-3 to 5 %) on one compound object
-    above a ground slab; then one timed 512 x 512 frame: G-buffer from the exact scene, one
-    shadow ray and 16 cosine-weighted AO rays per pixel, the field's answers (two-pass
-    hash query), the per-pixel maps.  Quality against the same rays cast exactly."""
+    """The renderer's use of the field (shadows, AO and one bounce; the paper's Table VI
+    analogue): the paper's hash-grid field distilled by its recipe (`steps` steps of 16,384
+    fresh GPU-sampled rays, 30 % self-consistency points, cosine lr from 3e-3 to 5 %) on one
+    compound object above a ground slab; then one timed 512 x 512 frame: G-buffer from the
+    exact scene, one shadow ray and 16 cosine-weighted hemisphere rays per pixel, the field's
+    answers (two-pass hash query), the per-pixel shadow and AO maps and the one-bounce term
+    (the radiance each hemisphere ray sees: a seeded surface-radiance grid at its hit point, or
+    the sky).  Quality against the same rays cast exactly."""
     import time
     sc = I.scene_object(8, 5)
     desc = I.HASH_PAPER
@@ -592,21 +594,26 @@ def shade_leg(torch, ddf, I, dev, timer, steps):
     qws = torch.empty(ddf.hash_query_workspace_bytes(desc, P * (1 + K)), dtype=torch.uint8, device=dev)
     res = {}
 
+    radiance = torch.from_numpy(I.radiance_grid(I.RADIANCE_RES, 49)).to(dev)
+
     def frame():
         gb, hit = ddf.primary_gbuffer(view, prims)
         ddf.secondary_rays(gb, hit, I.SHADE_LIGHT, K, u, I.NORMAL_OFFSET, out=rays)
         tf, xf = ddf.hash_query(desc, p, rays, ws=qws)
         sh, ao = ddf.shade(tf, gb, hit, I.SHADE_LIGHT, K, I.NORMAL_OFFSET, xi=xf)
-        res.update(gb=gb, hit=hit, sh=sh, ao=ao)
+        gi = ddf.bounce(tf, rays, hit, K, radiance, I.BOX_HALF, I.SKY, xi=xf)
+        res.update(gb=gb, hit=hit, sh=sh, ao=ao, gi=gi)
     for _ in range(2):
         frame()
     torch.cuda.synchronize()
     ms = timer.time(frame, 10)
     tg, rh = ddf.cast_targets(prims, rays)
     shr, aor = ddf.shade(tg, res["gb"], res["hit"], I.SHADE_LIGHT, K, I.NORMAL_OFFSET, ray_hit=rh)
+    gir = ddf.bounce(tg, rays, res["hit"], K, radiance, I.BOX_HALF, I.SKY, ray_hit=rh)
     torch.cuda.synchronize()
     hm = res["hit"].cpu().numpy().astype(bool)
-    sh, ao, shr, aor = (x.cpu().numpy().astype(np.float64)[hm] for x in (res["sh"], res["ao"], shr, aor))
+    sh, ao, gi, shr, aor, gir = (x.cpu().numpy().astype(np.float64)[hm]
+                                 for x in (res["sh"], res["ao"], res["gi"], shr, aor, gir))
 
     def psnr(a, b):
         mse = float(np.mean((a - b) ** 2))
@@ -617,7 +624,9 @@ def shade_leg(torch, ddf, I, dev, timer, steps):
             "frame": f"{view.width}x{view.height}, 1 shadow + {K} AO rays per pixel", "frame_ms": ms,
             "secondary_rays": n_rays, "secondary_rays_per_s": n_rays / (ms * 1e-3),
             "pixels_hit": int(hm.sum()), "shadow_psnr_db": psnr(sh, shr), "ao_psnr_db": psnr(ao, aor),
-            "ao_mae": float(np.mean(np.abs(ao - aor))), "paper_table6": {"shadow_psnr_db": 30.3, "ao_psnr_db": 21.3}}
+            "ao_mae": float(np.mean(np.abs(ao - aor))), "bounce_psnr_db": psnr(gi, gir),
+            "bounce_mae": float(np.mean(np.abs(gi - gir))),
+            "paper_table6": {"shadow_psnr_db": 30.3, "ao_psnr_db": 21.3}}
 
 
 def fit_sdf(torch, ddf, I, dev, scene, steps=400, batch=65536, prec="bf16", seed=100):

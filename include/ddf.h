@@ -393,6 +393,24 @@ int ddf_shade(const float* t, const float* xi, const uint8_t* ray_hit, const flo
               int64_t n_px, const float* light, int32_t n_ao, float offset, float ao_radius, float* shadow, float* ao,
               void* stream);
 
+/* One bounce of global illumination (Sec. I: a bounce query asks what a surface point sees in
+ * some direction; the renderer's use of the oracle, Sec. IV-F): per pixel, the mean over its
+ * n_ao cosine-weighted hemisphere rays (rays i (1 + n_ao) + 1 .. + n_ao of ddf_secondary_rays;
+ * cosine-weighted, so each carries the same weight for a diffuse surface) of the radiance the
+ * ray sees:
+ *   a hit (xi > 0.5, or ray_hit set): the surface radiance at o + t d, trilinear in the vertex
+ *     grid radiance over [-box_half, box_half]^3 (the point clamped to the box);
+ *   a miss: the sky, sky_lo + (sky_hi - sky_lo) (d_y + 1) / 2.
+ *   t, and exactly one of xi / ray_hit   [n_px (1 + n_ao)], the answers to the secondary rays.
+ *   rays        [6][n_px (1 + n_ao)] the secondary rays.   hit [n_px] primary hits (G-buffer).
+ *   radiance    device float32 [res][res][res], vertex (x, y, z) at index x + res (y + res z),
+ *               vertex coordinate -box_half + 2 box_half j / (res - 1); 2 <= res <= 1024.
+ *   gi          device float32 [n_px]: the bounce term, 0 for background pixels.
+ * 0 <= n_ao <= 1024 (n_ao = 0 gives 0), n_px (1 + n_ao) <= 2^31 - 1. */
+int ddf_bounce(const float* t, const float* xi, const uint8_t* ray_hit, const float* rays, const uint8_t* hit,
+               int64_t n_px, int32_t n_ao, const float* radiance, int32_t res, float box_half, float sky_lo,
+               float sky_hi, float* gi, void* stream);
+
 /* ------------------------------------------------------------------ training rays */
 
 /* Training rays [6][n] on the GPU (Sec. III-B: rays from the surface in every direction,

@@ -18,6 +18,11 @@ ambient occlusion compared with a reference ray tracer, Table VI):
   mean of their hit flags (within ao_radius).
 * The field answers (t, xi); a ray counts as hitting when xi > 0.5.  The reference
   answers with the exact first hit (xi = 1 on a hit, 0 on a miss).
+* One bounce of global illumination (Sec. I: a bounce query asks what a surface point sees
+  in some direction): the pixel's K hemisphere rays are cosine-weighted, so for a diffuse
+  surface each carries the same weight, and the bounce term is the mean over them of the
+  radiance each ray sees: the surface radiance at its hit point o + t d when it hits, the sky
+  when it misses.
 * Error measures over the pixels with a primary hit: PSNR = 10 log10(1 / MSE) of maps in
   [0, 1], and the mean absolute error of the AO map.
 
@@ -33,6 +38,11 @@ Readings where the paper is silent (each also listed in the design notes):
   (infinite: every hit).
 * Background pixels (no primary hit) get shadow 0 and AO 0 and are left out of the
   error measures.
+* The scene's outgoing surface radiance is given as values at the vertices of a res^3 grid
+  over the object box [-h, h]^3 (a stand-in for the appearance a renderer would read at the
+  hit point; the paper's renderer reads the Gaussians there), interpolated trilinearly, a
+  point outside the box clamped to it; the sky seen by a missing ray of direction d is
+  sky_lo + (sky_hi - sky_lo) (d_y + 1) / 2.  Background pixels get a bounce term of 0.
 """
 from __future__ import annotations
 
@@ -161,3 +171,48 @@ def psnr(a, b, mask):
 def mae(a, b, mask):
     m = np.asarray(mask, dtype=bool)
     return float(np.mean(np.abs(np.asarray(a, dtype=np.float64)[m] - np.asarray(b, dtype=np.float64)[m])))
+
+
+def surface_radiance(q, radiance, box_half):
+    """Trilinear interpolation of the vertex grid radiance [res, res, res] (indexed [z, y, x])
+    at points q [N, 3] of the box [-box_half, box_half]^3 (clamped to it)."""
+    R = np.asarray(radiance, dtype=np.float64)
+    res = R.shape[0]
+    p = np.clip((np.asarray(q, dtype=np.float64) + box_half) / (2 * box_half), 0.0, 1.0)
+    s = p * (res - 1)
+    c = np.minimum(np.floor(s), res - 2).astype(np.int64)
+    w = s - c
+    out = np.zeros(len(p))
+    for k in range(8):
+        dx, dy, dz = k & 1, (k >> 1) & 1, (k >> 2) & 1
+        wt = (w[:, 0] if dx else 1 - w[:, 0]) * (w[:, 1] if dy else 1 - w[:, 1]) * (w[:, 2] if dz else 1 - w[:, 2])
+        out += wt * R[c[:, 2] + dz, c[:, 1] + dy, c[:, 0] + dx]
+    return out
+
+
+def sky(d, sky_lo, sky_hi):
+    """Radiance seen by a ray of unit direction d [N, 3] that hits nothing."""
+    return sky_lo + (sky_hi - sky_lo) * (np.asarray(d, dtype=np.float64)[:, 1] + 1.0) / 2.0
+
+
+def bounce(t, hitflag, rays, hit, n_ao, radiance, box_half, sky_lo, sky_hi):
+    """The one-bounce term [P]: per pixel, the mean over its K hemisphere rays (rays
+    [P (1 + K), 6], pixel-major, the shadow ray first and skipped) of the radiance each ray
+    sees, surface_radiance(o + t d) on a hit, sky(d) on a miss; 0 for background pixels."""
+    hit = np.asarray(hit, dtype=bool)
+    P = len(hit)
+    if n_ao == 0:
+        return np.zeros(P)
+    r = np.asarray(rays, dtype=np.float64).reshape(P, 1 + n_ao, 6)[:, 1:].reshape(-1, 6)
+    tt = np.asarray(t, dtype=np.float64).reshape(P, 1 + n_ao)[:, 1:].reshape(-1)
+    f = np.asarray(hitflag, dtype=bool).reshape(P, 1 + n_ao)[:, 1:].reshape(-1)
+    q = r[:, 0:3] + np.where(f, tt, 0.0)[:, None] * r[:, 3:6]
+    L = np.where(f, surface_radiance(q, radiance, box_half), sky(r[:, 3:6], sky_lo, sky_hi))
+    return np.where(hit, L.reshape(P, n_ao).mean(axis=1), 0.0)
+
+
+def reference_bounce(scene, rays, hit, n_ao, radiance, box_half, sky_lo, sky_hi):
+    """The reference one-bounce map: the same rays answered by exact ray casting."""
+    r = np.asarray(rays, dtype=np.float64)
+    t, h, _ = G.intersect(scene, r[:, 0:3], r[:, 3:6])
+    return bounce(t, h, r, hit, n_ao, radiance, box_half, sky_lo, sky_hi)

@@ -173,6 +173,59 @@ __global__ __launch_bounds__(kShadeThreads) void shade_kernel(const float* __res
   ao[i] = a;
 }
 
+// Trilinear surface radiance of the res^3 vertex grid R ([z][y][x]) over [-h, h]^3 at q (clamped
+// to the box; a NaN coordinate clamps to the low face, so every read stays in the grid).
+__device__ __forceinline__ float radiance_at(const float* __restrict__ R, int res, float h, float q0, float q1,
+                                             float q2) {
+  const float inv = 0.5f / h, sc = (float)(res - 1);
+  const float s0 = fminf(fmaxf((q0 + h) * inv, 0.f), 1.f) * sc;
+  const float s1 = fminf(fmaxf((q1 + h) * inv, 0.f), 1.f) * sc;
+  const float s2 = fminf(fmaxf((q2 + h) * inv, 0.f), 1.f) * sc;
+  const int c0 = min((int)floorf(s0), res - 2), c1 = min((int)floorf(s1), res - 2), c2 = min((int)floorf(s2), res - 2);
+  const float w0 = s0 - (float)c0, w1 = s1 - (float)c1, w2 = s2 - (float)c2;
+  const int64_t sy = res, sz = (int64_t)res * res;
+  const float* b = R + c2 * sz + c1 * sy + c0;
+  const float x00 = b[0] + w0 * (b[1] - b[0]);
+  const float x10 = b[sy] + w0 * (b[sy + 1] - b[sy]);
+  const float x01 = b[sz] + w0 * (b[sz + 1] - b[sz]);
+  const float x11 = b[sz + sy] + w0 * (b[sz + sy + 1] - b[sz + sy]);
+  const float y0 = x00 + w1 * (x10 - x00), y1 = x01 + w1 * (x11 - x01);
+  return y0 + w2 * (y1 - y0);
+}
+
+// One bounce, one pixel per thread: the mean over the pixel's K hemisphere rays (rays
+// i (1 + K) + 1 .. i (1 + K) + K of the pixel-major secondary rays) of the radiance each ray
+// sees, the surface radiance at o + t d when it hits, the sky when it misses.
+__global__ __launch_bounds__(kShadeThreads) void bounce_kernel(const float* __restrict__ t,
+                                                               const float* __restrict__ xi,
+                                                               const uint8_t* __restrict__ ray_hit,
+                                                               const float* __restrict__ rays,
+                                                               const uint8_t* __restrict__ hit, int64_t P, int K,
+                                                               const float* __restrict__ R, int res, float h,
+                                                               float sky_lo, float sky_hi, float* __restrict__ gi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  float acc = 0.f;
+  if (hit[i]) {
+    const int64_t N = P * (1 + K);
+    for (int k = 1; k <= K; ++k) {
+      const int64_t g = i * (1 + K) + k;
+      const float d0 = rays[3 * N + g], d1 = rays[4 * N + g], d2 = rays[5 * N + g];
+      const bool hk = xi ? xi[g] > 0.5f : ray_hit[g] != 0;
+      float L;
+      if (hk) {
+        const float tk = t[g];
+        L = radiance_at(R, res, h, fmaf(tk, d0, rays[g]), fmaf(tk, d1, rays[N + g]), fmaf(tk, d2, rays[2 * N + g]));
+      } else {
+        L = sky_lo + (sky_hi - sky_lo) * (d1 + 1.f) * 0.5f;
+      }
+      acc += L;
+    }
+    acc = K > 0 ? acc / (float)K : 0.f;
+  }
+  gi[i] = acc;
+}
+
 // ---- training rays: area-weighted surface rays and free rays, with rejection
 
 // Cumulative surface-area weights of the primitives (Knud Thomsen's ellipsoid area
@@ -354,6 +407,29 @@ int ddf_shade(const float* t, const float* xi, const uint8_t* ray_hit, const flo
                                                                           light[1], light[2], n_ao, offset, ao_radius,
                                                                           shadow, ao);
   return hip_status(hipGetLastError(), "ddf_shade launch");
+}
+
+int ddf_bounce(const float* t, const float* xi, const uint8_t* ray_hit, const float* rays, const uint8_t* hit,
+               int64_t n_px, int32_t n_ao, const float* radiance, int32_t res, float box_half, float sky_lo,
+               float sky_hi, float* gi, void* stream) {
+  int rc;
+  if (n_ao < 0 || n_ao > 1024) return fail(DDF_ERR_INVALID_ARG, "n_ao = %d out of 0..1024", n_ao);
+  if (n_px < 0 || n_px * (1 + n_ao) > (int64_t)INT32_MAX)
+    return fail(DDF_ERR_INVALID_ARG, "n_px = %lld out of range", (long long)n_px);
+  if (res < 2 || res > 1024) return fail(DDF_ERR_INVALID_ARG, "res = %d out of 2..1024", res);
+  if (!(box_half > 0.f) || !std::isfinite(box_half)) return fail(DDF_ERR_INVALID_ARG, "box_half must be > 0");
+  if (!std::isfinite(sky_lo) || !std::isfinite(sky_hi)) return fail(DDF_ERR_INVALID_ARG, "sky radiance not finite");
+  if ((xi == nullptr) == (ray_hit == nullptr)) return fail(DDF_ERR_INVALID_ARG, "pass exactly one of xi and ray_hit");
+  if (n_px == 0) return DDF_OK;
+  if ((rc = check_ptr(t, "t")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(hit, "hit")) ||
+      (rc = check_ptr(radiance, "radiance")) || (rc = check_ptr(gi, "gi")))
+    return rc;
+  if ((rc = check_ptr(xi ? (const void*)xi : (const void*)ray_hit, xi ? "xi" : "ray_hit"))) return rc;
+  g_err_clear();
+  bounce_kernel<<<grid_for(n_px), kShadeThreads, 0, (hipStream_t)stream>>>(t, xi, ray_hit, rays, hit, n_px, n_ao,
+                                                                           radiance, res, box_half, sky_lo, sky_hi,
+                                                                           gi);
+  return hip_status(hipGetLastError(), "ddf_bounce launch");
 }
 
 int ddf_prim_area_cdf(const float* prims, int32_t n_prims, float* cdf, void* stream) {

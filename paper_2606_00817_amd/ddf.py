@@ -98,6 +98,8 @@ SIGNATURES = {
                                           ctypes.c_float, _P, _P]),
     "ddf_shade": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
                                  ctypes.c_float, ctypes.c_float, _P, _P, _P]),
+    "ddf_bounce": (ctypes.c_int, [_P, _P, _P, _P, _P, _I64, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, _P, _P]),
     "ddf_prim_area_cdf": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P]),
     "ddf_sample_rays": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _I64, ctypes.c_int32, ctypes.c_float,
                                        ctypes.c_float, ctypes.c_int32, _P, _P]),
@@ -576,6 +578,22 @@ def shade(t: torch.Tensor, gbuf: torch.Tensor, hit: torch.Tensor, light, n_ao: i
     _check(lib().ddf_shade(_ptr(t), _ptr(xi), _ptr(ray_hit), _ptr(gbuf), _ptr(hit), P, L, int(n_ao), float(offset),
                            float(ao_radius), _ptr(shadow), _ptr(ao), _stream()))
     return shadow, ao
+
+
+def bounce(t: torch.Tensor, rays: torch.Tensor, hit: torch.Tensor, n_ao: int, radiance: torch.Tensor,
+           box_half: float, sky, xi: torch.Tensor | None = None, ray_hit: torch.Tensor | None = None,
+           out: torch.Tensor | None = None) -> torch.Tensor:
+    """The one-bounce term [P] from the answers t and xi (the field) or ray_hit (the exact cast)
+    to the secondary rays; radiance [res, res, res] the surface-radiance vertex grid."""
+    _dev(t, torch.float32, "t")
+    _dev(rays, torch.float32, "rays")
+    _dev(radiance, torch.float32, "radiance")
+    P = hit.shape[0]
+    gi = torch.empty(P, dtype=torch.float32, device=t.device) if out is None else out
+    _check(lib().ddf_bounce(_ptr(t), _ptr(xi), _ptr(ray_hit), _ptr(rays), _ptr(hit), P, int(n_ao), _ptr(radiance),
+                            int(radiance.shape[0]), float(box_half), float(sky[0]), float(sky[1]), _ptr(gi),
+                            _stream()))
+    return gi
 
 
 def prim_area_cdf(prims: torch.Tensor) -> torch.Tensor:

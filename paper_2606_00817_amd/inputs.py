@@ -456,6 +456,8 @@ class View:
 
 
 SHADE_LIGHT = (1.2, 2.8, 0.8)   # point light of the shading workload (outside the box)
+SKY = (0.2, 1.0)                # sky radiance at the nadir and the zenith (one-bounce term)
+RADIANCE_RES = 32               # vertices per axis of the surface-radiance grid
 AO_RAYS = 16                    # AO rays per pixel of the shading workload
 
 
@@ -484,3 +486,19 @@ def scene_object(n: int, seed: int) -> Scene:
     rots = _random_rotations(rng, n)
     return Scene(np.concatenate([[[0.0, -1.02, 0.0]], c]), np.concatenate([[[1.45, 0.02, 1.45]], a]),
                  np.concatenate([np.eye(3)[None], rots]))
+
+
+def radiance_grid(res: int, seed: int) -> np.ndarray:
+    """A smooth surface-radiance field in [0.1, 0.9] sampled at the vertices of a res^3 grid
+    over the object box, float32 [res (z)][res (y)][res (x)]: the mean of four random plane
+    waves of 1-3 periods across the box (a stand-in for the captured appearance)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = np.linspace(-BOX_HALF, BOX_HALF, res)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    pts = np.stack([x, y, z], axis=-1)
+    acc = np.zeros(pts.shape[:-1])
+    for _ in range(4):
+        k = rng.standard_normal(3)
+        k *= rng.uniform(1.0, 3.0) * 2 * np.pi / (2 * BOX_HALF) / np.linalg.norm(k)
+        acc += np.cos(pts @ k + rng.uniform(0, 2 * np.pi))
+    return np.ascontiguousarray((0.5 + 0.1 * acc).astype(np.float32))

@@ -125,6 +125,49 @@ def test_shade_argument_errors():
                             torch.zeros((1, 16), device=dev))
 
 
+@pytest.mark.parametrize("answers", ["field", "exact"])
+def test_bounce_matches_oracle(answers):
+    """The one-bounce term against the oracle's on the same answers and rays: float32 hit
+    points and trilinear weights, a sum of K terms in [0, 1] (observed ~1e-7)."""
+    dev = cuda()
+    P, K = 3001, 8
+    rng = np.random.default_rng(50)
+    hit = np.ones(P, dtype=np.uint8)
+    hit[::7] = 0
+    o = rng.uniform(-1.4, 1.4, (P * (1 + K), 3))
+    d = rng.standard_normal((P * (1 + K), 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rays = np.ascontiguousarray(np.concatenate([o, d], axis=1).T.astype(np.float32))
+    t = rng.uniform(0, 4, P * (1 + K)).astype(np.float32)
+    xi = rng.uniform(0, 1, P * (1 + K)).astype(np.float32)
+    xi[::13] = 0.5                                   # exactly at the threshold: a miss
+    rh = (rng.uniform(size=P * (1 + K)) < 0.4).astype(np.uint8)
+    R = I.radiance_grid(I.RADIANCE_RES, 49)
+    kw = {"xi": _t(xi, dev)} if answers == "field" else {"ray_hit": _t(rh, dev)}
+    gi = ddf.bounce(_t(t, dev), _t(rays, dev), _t(hit, dev), K, _t(R, dev), I.BOX_HALF, I.SKY, **kw)
+    torch.cuda.synchronize()
+    flag = xi > 0.5 if answers == "field" else rh.astype(bool)
+    g64 = S.bounce(t, flag, rays.T.astype(np.float64), hit.astype(bool), K, R, I.BOX_HALF, *I.SKY)
+    err = np.abs(gi.cpu().numpy().astype(np.float64) - g64)
+    print(f"bounce ({answers}): max |d gi| {err.max():.2e}")
+    assert err.max() <= 2e-6
+    assert (gi.cpu().numpy()[hit == 0] == 0).all()
+
+
+def test_bounce_argument_errors():
+    dev = cuda()
+    P, K = 4, 2
+    t = torch.zeros(P * (1 + K), device=dev)
+    rays = torch.zeros((6, P * (1 + K)), device=dev)
+    hit = torch.ones(P, dtype=torch.uint8, device=dev)
+    with pytest.raises(ddf.DDFError, match="exactly one"):
+        ddf.bounce(t, rays, hit, K, torch.zeros((2, 2, 2), device=dev), I.BOX_HALF, I.SKY)
+    with pytest.raises(ddf.DDFError, match="res"):
+        ddf.bounce(t, rays, hit, K, torch.zeros((1, 1, 1), device=dev), I.BOX_HALF, I.SKY, xi=t)
+    with pytest.raises(ddf.DDFError, match="box_half"):
+        ddf.bounce(t, rays, hit, K, torch.zeros((2, 2, 2), device=dev), 0.0, I.SKY, xi=t)
+
+
 def test_reference_maps_match_oracle():
     """The reference pipeline on the GPU (G-buffer, secondary rays, exact cast, reduction)
     against the oracle's: the maps differ only where float32 points move a ray across an
@@ -146,8 +189,15 @@ def test_reference_maps_match_oracle():
     m = hit.cpu().numpy().astype(bool) & h64
     ds = np.abs(sh.cpu().numpy() - s64)[m]
     da = np.abs(ao.cpu().numpy() - a64)[m]
-    print(f"reference maps: shadow mismatches {int((ds > 0).sum())} / {m.sum()}, AO MAE {da.mean():.2e}")
-    assert (ds > 0).mean() < 0.01 and da.mean() < 0.01
+    R = I.radiance_grid(I.RADIANCE_RES, 49)
+    gi = ddf.bounce(tg, rays, hit, K, _t(R, dev), I.BOX_HALF, I.SKY, ray_hit=rh)
+    torch.cuda.synchronize()
+    rays64 = S.secondary_rays(p, n, I.SHADE_LIGHT, K, u.astype(np.float64), OFF)
+    g64 = S.reference_bounce(sc, rays64, h64, K, R, I.BOX_HALF, *I.SKY)
+    dg = np.abs(gi.cpu().numpy() - g64)[m]
+    print(f"reference maps: shadow mismatches {int((ds > 0).sum())} / {m.sum()}, AO MAE {da.mean():.2e}, "
+          f"bounce MAE {dg.mean():.2e}")
+    assert (ds > 0).mean() < 0.01 and da.mean() < 0.01 and dg.mean() < 0.01
 
 
 def test_trained_hash_field_shading():
@@ -202,6 +252,15 @@ def test_trained_hash_field_shading():
     ps = S.psnr(sh.cpu().numpy(), shr.cpu().numpy(), hm)
     pa = S.psnr(ao.cpu().numpy(), aor.cpu().numpy(), hm)
     ma = S.mae(ao.cpu().numpy(), aor.cpu().numpy(), hm)
-    print(f"trained hash field ({steps} steps): shadow PSNR {ps:.2f} dB, AO PSNR {pa:.2f} dB, AO MAE {ma:.4f}; "
-          f"shadowed {shr.cpu().numpy()[hm].mean():.3f}, mean AO {aor.cpu().numpy()[hm].mean():.3f}")
-    assert ps > 9.0 and pa > 18.0 and ma < 0.06
+    R = _t(I.radiance_grid(I.RADIANCE_RES, 49), dev)
+    gf = ddf.bounce(tf, rays, hit, K, R, I.BOX_HALF, I.SKY, xi=xf)
+    gr = ddf.bounce(tg, rays, hit, K, R, I.BOX_HALF, I.SKY, ray_hit=rh)
+    torch.cuda.synchronize()
+    g64 = S.bounce(tf.cpu().numpy(), xf.cpu().numpy() > 0.5, rays.cpu().numpy().T.astype(np.float64), hm, K,
+                   R.cpu().numpy(), I.BOX_HALF, *I.SKY)
+    assert np.abs(gf.cpu().numpy() - g64).max() <= 2e-6
+    pg = S.psnr(gf.cpu().numpy(), gr.cpu().numpy(), hm)
+    print(f"trained hash field ({steps} steps): shadow PSNR {ps:.2f} dB, AO PSNR {pa:.2f} dB, AO MAE {ma:.4f}, "
+          f"bounce PSNR {pg:.2f} dB; shadowed {shr.cpu().numpy()[hm].mean():.3f}, mean AO "
+          f"{aor.cpu().numpy()[hm].mean():.3f}")
+    assert ps > 9.0 and pa > 18.0 and ma < 0.06 and pg > 18.0

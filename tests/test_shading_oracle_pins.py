@@ -162,3 +162,72 @@ def test_secondary_rays_layout():
     ca = np.einsum('pki,pi->pk', rays[:, 1:, 3:6], nrm)
     assert np.allclose(ca, np.sqrt(1 - u[0].reshape(50, K)))
     assert np.allclose(np.linalg.norm(rays[:, :, 3:6], axis=2), 1.0)
+
+
+# ---- the one-bounce term
+
+def _linear_grid(res, coef):
+    """Vertex grid of the linear radiance a + b x + c y + d z over the box ([z][y][x])."""
+    g = np.linspace(-I.BOX_HALF, I.BOX_HALF, res)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    return coef[0] + coef[1] * x + coef[2] * y + coef[3] * z
+
+
+def test_surface_radiance_reproduces_a_linear_field_and_clamps():
+    """Trilinear interpolation is exact for a linear field; a point outside the box reads the
+    value on the box face nearest to it (the clamp)."""
+    coef = (0.5, 0.1, -0.05, 0.02)
+    R = _linear_grid(7, coef)
+    rng = np.random.default_rng(3)
+    q = rng.uniform(-I.BOX_HALF, I.BOX_HALF, (500, 3))
+    ref = coef[0] + q @ np.array(coef[1:])
+    np.testing.assert_allclose(S.surface_radiance(q, R, I.BOX_HALF), ref, atol=1e-13)
+    out = np.array([[2.5, 0.3, -0.2], [-9.0, -9.0, 9.0]])
+    cl = np.clip(out, -I.BOX_HALF, I.BOX_HALF)
+    np.testing.assert_allclose(S.surface_radiance(out, R, I.BOX_HALF), coef[0] + cl @ np.array(coef[1:]), atol=1e-13)
+
+
+def test_bounce_sees_the_hit_point_or_the_sky():
+    """A pixel whose two hemisphere rays are cast exactly: one hits a sphere head on at a known
+    point (radiance of the linear field there), one escapes straight up (the zenith sky)."""
+    coef = (0.4, 0.1, 0.2, -0.3)
+    R = _linear_grid(5, coef)
+    sc = I.Scene(np.array([[0.0, 0.0, 0.5]]), np.array([[0.25, 0.25, 0.25]]), np.eye(3)[None])
+    # pixel-major rays of one pixel: a shadow ray (skipped), then the two hemisphere rays
+    rays = np.array([[0, 0, -1.0, 0, 1, 0],        # shadow ray (ignored by the bounce term)
+                     [0, 0, -1.0, 0, 0, 1],        # hits the sphere at (0, 0, 0.25)
+                     [0, 0, -1.0, 0, 1, 0]])       # misses: zenith
+    lo, hi = 0.2, 1.0
+    gi = S.reference_bounce(sc, rays, np.ones(1, bool), 2, R, I.BOX_HALF, lo, hi)
+    expect = 0.5 * ((coef[0] + coef[3] * 0.25) + hi)
+    assert abs(gi[0] - expect) < 1e-12
+    # a background pixel gets 0; with no hemisphere rays the term is 0
+    assert S.reference_bounce(sc, rays, np.zeros(1, bool), 2, R, I.BOX_HALF, lo, hi)[0] == 0.0
+    assert S.bounce(np.zeros(1), np.zeros(1, bool), rays[:1], np.ones(1, bool), 0, R, I.BOX_HALF, lo, hi)[0] == 0.0
+
+
+def test_bounce_under_an_open_sky():
+    """A horizontal point with nothing above it: the cosine-weighted mean of the sky gradient is
+    lo + (hi - lo) (E[d_y] + 1) / 2 with E[d_y] = 2/3 over the cosine-weighted hemisphere, so
+    the bounce term is lo + (5/6) (hi - lo); the oracle's own secondary rays (Malley) get there
+    within Monte Carlo error."""
+    K = 200000
+    u = I.uniforms(2, K, 92).astype(np.float64)
+    sc = I.Scene(np.array([[0.0, -5.0, 0.0]]), np.array([[0.1, 0.1, 0.1]]), np.eye(3)[None])   # below: never hit
+    rays = S.secondary_rays(np.zeros((1, 3)), np.array([[0.0, 1.0, 0.0]]), (0.0, 3.0, 0.0), K, u, 1e-3)
+    lo, hi = 0.2, 1.0
+    gi = S.reference_bounce(sc, rays, np.ones(1, bool), K, np.zeros((2, 2, 2)), I.BOX_HALF, lo, hi)
+    # d_y = sqrt(1 - u1) under Malley's method: variance of (hi - lo) d_y / 2 over the hemisphere
+    sd = (hi - lo) / 2 * math.sqrt(1 / 2 - 4 / 9)
+    assert abs(gi[0] - (lo + 5 / 6 * (hi - lo))) < 5 * sd / math.sqrt(K)
+
+
+def test_bounce_constant_radiance_and_full_occlusion():
+    """A point at the centre of a closed sphere sees the surface in every direction: with a
+    constant radiance c the bounce term is exactly c."""
+    sc = I.Scene(np.zeros((1, 3)), np.array([[1.2, 1.2, 1.2]]), np.eye(3)[None])
+    K = 64
+    u = I.uniforms(2, K, 93).astype(np.float64)
+    rays = S.secondary_rays(np.zeros((1, 3)), np.array([[0.0, 0.0, 1.0]]), (0.0, 0.5, 0.0), K, u, 0.0)
+    gi = S.reference_bounce(sc, rays, np.ones(1, bool), K, np.full((3, 3, 3), 0.37), I.BOX_HALF, 0.0, 1.0)
+    assert abs(gi[0] - 0.37) < 1e-12
