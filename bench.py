@@ -662,46 +662,50 @@ def fit_sdf(torch, ddf, I, dev, scene, steps=400, batch=65536, prec="bf16", seed
 def trace_leg(torch, ddf, I, dev, rays, timer, out, scene, fit_steps=400):
     """Sphere tracing of a 12 x 1024 signed-distance MLP along the same shadow rays.
 
-    The SDF MLP is fitted to the scene first (fit_sdf); the trace runs in fp32 with at most
-    128 steps, hit at |s| < 1e-4, miss beyond t = 6; then once more in bf16 with the same
-    settings (the same-precision comparison with the bf16 DDF query)."""
+    The SDF MLP is fitted to the scene first (fit_sdf).  fp32, at most 128 steps, miss beyond
+    t = 6: the persistent lane-refill trace (one launch) at hit thresholds 1e-2, 1e-3 and 1e-4,
+    each with its unconverged share and its ratio to the DDF query of the same rays; the
+    step-synchronous trace at 1e-4 (same answers bit for bit, its time for comparison); and the
+    bf16 trace at 1e-4 (the same-precision comparison with the bf16 DDF query)."""
     desc = I.NET_SDF
     (packed, packed_bf16), fit = fit_sdf(torch, ddf, I, dev, scene, steps=fit_steps)
     n = rays.shape[1]
-    ws = torch.empty(int(ddf.lib().sdf_trace_workspace_bytes(n)), dtype=torch.uint8, device=dev)
-    ddf.sphere_trace(desc, "fp32", packed, rays, 128, 1e-4, 6.0, ws=ws)
-    torch.cuda.synchronize()
-    ms = timer.time(lambda: ddf.sphere_trace(desc, "fp32", packed, rays, 128, 1e-4, 6.0, ws=ws), 1)
-    t, hit, steps = ddf.sphere_trace(desc, "fp32", packed, rays, 128, 1e-4, 6.0, ws=ws)
     prims = torch.from_numpy(ddf.scene_prims(scene)).to(dev)
     tg, hg = ddf.cast_targets(prims, rays)
-    st = steps.float()
     prec = out   # the shadow leg's query timings on the same rays, per precision
-    hist = torch.bincount(steps.long().clamp(0, 128), minlength=129).cpu().numpy()
     edges = [1, 2, 4, 8, 16, 32, 64, 128, 129]
-    res = {"sdf": "12x1024 SDF MLP (L=10, 63 features) fitted to the scene's distance bound",
-           "steps_histogram": {f"{edges[i]}-{edges[i + 1] - 1}": int(hist[edges[i]:edges[i + 1]].sum())
-                               for i in range(len(edges) - 1)},
-           "fit": fit, "precision": "fp32", "max_steps": 128, "hit_eps": 1e-4, "t_max": 6.0,
-           "ms": ms, "rays_per_s": n / (ms * 1e-3), "mean_steps": float(st.mean().item()),
-           "p50_steps": float(st.median().item()), "max_steps_used": int(steps.max().item()),
-           "unconverged_fraction": float((steps >= 128).float().mean().item() - 0.0),
-           "hit_rate": float(hit.float().mean().item()),
-           "hit_agreement_vs_exact_cast": float((hit == hg).float().mean().item())}
-    for p in ("fp32", "bf16", "fp8"):
-        msp = prec.get(p, {}).get("ms")
-        if msp:
-            res[f"speedup_vs_ddf_{p}"] = ms / msp
-    # the bf16 trace (one timed run)
-    ms16 = timer.time(lambda: ddf.sphere_trace(desc, "bf16", packed_bf16, rays, 128, 1e-4, 6.0, ws=ws), 1)
-    t16, hit16, steps16 = ddf.sphere_trace(desc, "bf16", packed_bf16, rays, 128, 1e-4, 6.0, ws=ws)
-    s16 = steps16.float()
-    res["bf16"] = {"ms": ms16, "rays_per_s": n / (ms16 * 1e-3), "mean_steps": float(s16.mean().item()),
-                   "unconverged_fraction": float((steps16 >= 128).float().mean().item()),
-                   "hit_agreement_vs_exact_cast": float((hit16 == hg).float().mean().item())}
-    msb = prec.get("bf16", {}).get("ms")
-    if msb:
-        res["bf16"]["speedup_vs_ddf_bf16"] = ms16 / msb
+
+    def stats(ms, res_t):
+        t, hit, steps = res_t
+        st = steps.float()
+        hist = torch.bincount(steps.long().clamp(0, 128), minlength=129).cpu().numpy()
+        r = {"ms": ms, "rays_per_s": n / (ms * 1e-3), "mean_steps": float(st.mean().item()),
+             "p50_steps": float(st.median().item()), "unconverged_fraction": float((steps >= 128).float().mean().item()),
+             "hit_rate": float(hit.float().mean().item()),
+             "hit_agreement_vs_exact_cast": float((hit == hg).float().mean().item()),
+             "steps_histogram": {f"{edges[i]}-{edges[i + 1] - 1}": int(hist[edges[i]:edges[i + 1]].sum())
+                                 for i in range(len(edges) - 1)}}
+        for p in ("fp32", "bf16", "fp8"):
+            msp = prec.get(p, {}).get("ms")
+            if msp:
+                r[f"speedup_vs_ddf_{p}"] = ms / msp
+        return r
+
+    res = {"sdf": "12x1024 SDF MLP (L=10, 63 features) fitted to the scene's distance bound", "fit": fit,
+           "max_steps": 128, "t_max": 6.0, "precision": "fp32", "pool": {}}
+    wsp = torch.empty(256, dtype=torch.uint8, device=dev)
+    for eps in (1e-2, 1e-3, 1e-4):
+        run = lambda: ddf.sphere_trace(desc, "fp32", packed, rays, 128, eps, 6.0, ws=wsp, pool=True)
+        ms = timer.time(run, 1)
+        res["pool"][f"{eps:g}"] = stats(ms, run())
+    ws = torch.empty(int(ddf.lib().sdf_trace_workspace_bytes(n)), dtype=torch.uint8, device=dev)
+    run = lambda: ddf.sphere_trace(desc, "fp32", packed, rays, 128, 1e-4, 6.0, ws=ws)
+    ms = timer.time(run, 1)
+    res["step_synchronous_1e-4"] = stats(ms, run())
+    run = lambda: ddf.sphere_trace(desc, "bf16", packed_bf16, rays, 128, 1e-4, 6.0, ws=wsp, pool=True)
+    ms16 = timer.time(run, 1)
+    r16 = stats(ms16, run())
+    res["bf16_pool_1e-4"] = {k: v for k, v in r16.items() if k != "steps_histogram"}
     return res
 
 

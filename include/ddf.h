@@ -212,6 +212,17 @@ int sdf_sphere_trace(const ddf_net_desc* desc, const void* packed, const float* 
                      int64_t n, int32_t max_steps, float hit_eps, float t_max, float* t,
                      uint8_t* hit, int32_t* steps, void* ws, size_t ws_bytes, void* stream);
 
+/* The same sphere trace as one persistent launch with lane refill (the baseline given its best
+ * form for this chip): one workgroup per compute unit holds a tile of ray slots for the whole
+ * trace; whenever rays finish (hit, t > t_max, or max_steps evaluations) their slots take the
+ * next rays of the pool, so every evaluation runs on a full tile until the pool is exhausted,
+ * with no per-step launches or active-list compaction.  Same arguments and results as
+ * sdf_sphere_trace, bit for bit (t, hit, steps); ws: device, >= 256 bytes (the pool counter),
+ * overwritten.  fp32 and bf16 nets of width 256, 512 or 1024 (else DDF_ERR_UNSUPPORTED). */
+int sdf_sphere_trace_pool(const ddf_net_desc* desc, const void* packed, const float* rays, int64_t n,
+                          int32_t max_steps, float hit_eps, float t_max, float* t, uint8_t* hit,
+                          int32_t* steps, void* ws, size_t ws_bytes, void* stream);
+
 /* The small-batch query (the sparse regime, ~1K-5K rays): bf16 nets of width 256, 512
  * or 1024 only.  One launch per layer with the layer's neurons split over workgroups (64
  * rays x 256 neurons each), so that a small batch still spreads over every CU; the

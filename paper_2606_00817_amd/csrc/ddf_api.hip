@@ -319,6 +319,29 @@ int ddf_fp8_act_scales(const ddf_net_desc* d, const void* packed_fp32, const flo
   return DDF_OK;
 }
 
+__global__ void pool_init_kernel(int64_t n, unsigned long long* pool, float* t, uint8_t* hit, int32_t* steps) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *pool = 0ull;
+  if (i < n) {
+    t[i] = 0.f;
+    hit[i] = 0;
+    if (steps) steps[i] = 0;
+  }
+}
+
+// Compute units of the current device (the persistent trace's grid: one workgroup per CU).
+static int device_cus() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0) c = 256;
+    cached[dev] = c;
+  }
+  return cached[dev];
+}
+
 size_t sdf_trace_workspace_bytes(int64_t n) {
   if (n < 0) return 0;
   // two active lists of n int32 and (max steps + 1) counters, max steps <= 4096
@@ -360,6 +383,37 @@ int sdf_sphere_trace(const ddf_net_desc* d, const void* packed, const float* ray
     if ((rc = hip_status(launch_forward(*d, a, n, st), "sphere-trace step launch"))) return rc;
   }
   return DDF_OK;
+}
+
+int sdf_sphere_trace_pool(const ddf_net_desc* d, const void* packed, const float* rays, int64_t n,
+                          int32_t max_steps, float hit_eps, float t_max, float* t, uint8_t* hit, int32_t* steps,
+                          void* ws, size_t ws_bytes, void* stream) {
+  int rc;
+  if ((rc = check_desc(d))) return rc;
+  if (d->n_in != 3 || d->n_out != 1) return fail(DDF_ERR_INVALID_ARG, "sphere tracing needs an SDF net (n_in 3, n_out 1)");
+  if (d->precision == DDF_FP8_E4M3 || d->width < 256)
+    return fail(DDF_ERR_UNSUPPORTED, "the persistent trace is built for fp32 and bf16 nets of width 256..1024");
+  if (n < 0 || n > (int64_t)INT32_MAX) return fail(DDF_ERR_INVALID_ARG, "n = %lld out of range", (long long)n);
+  if (max_steps < 1 || max_steps > 4096) return fail(DDF_ERR_INVALID_ARG, "max_steps must be in 1..4096");
+  if (!(hit_eps > 0.f) || !(t_max > 0.f)) return fail(DDF_ERR_INVALID_ARG, "hit_eps and t_max must be positive");
+  if (n == 0) return DDF_OK;
+  if ((rc = check_ptr(packed, "packed")) || (rc = check_ptr(rays, "rays")) || (rc = check_ptr(t, "t")) ||
+      (rc = check_ptr(hit, "hit")) || (rc = check_ptr(ws, "ws")))
+    return rc;
+  if (steps && (rc = check_ptr(steps, "steps"))) return rc;
+  if (ws_bytes < 256) return fail(DDF_ERR_WORKSPACE, "workspace %zu < 256 bytes", ws_bytes);
+  hipStream_t st = (hipStream_t)stream;
+  unsigned long long* pool = static_cast<unsigned long long*>(ws);
+  pool_init_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(n, pool, t, hit, steps);
+  if ((rc = hip_status(hipGetLastError(), "trace init"))) return rc;
+  FwdArgs a = base_args(*d, packed);
+  a.in = rays; a.n = n; a.stride = n; a.mode = kModePool;
+  a.t_state = t; a.hit = hit; a.steps = steps; a.hit_eps = hit_eps; a.t_max = t_max;
+  a.max_steps = max_steps; a.pool = pool;
+  const int64_t tiles = (n + geo_of(d->precision).rays_per_wg - 1) / geo_of(d->precision).rays_per_wg;
+  const int n_wg = (int)(tiles < device_cus() ? tiles : device_cus());
+  g_err[0] = 0;
+  return hip_status(launch_pool_trace(*d, a, n_wg, st), "persistent trace launch");
 }
 
 int ddf_cast_targets(const float* prims, int32_t n_prims, const float* rays, int64_t n, float* t_gt,

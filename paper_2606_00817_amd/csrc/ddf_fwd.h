@@ -12,7 +12,8 @@ enum FwdMode {
   kModeTrace = 3,   // one sphere-tracing step over the active-ray list
   kModeCalib = 4,   // query that records max h_l of hidden layers 1..n-1 (FP8 scales)
   kModeRecompute = 5,  // training: rerun hidden layers from a kept activation, keeping theirs
-  kModeHidden = 6      // the last hidden layer's float32 output h_n per ray, [n][width] in out0
+  kModeHidden = 6,     // the last hidden layer's float32 output h_n per ray, [n][width] in out0
+  kModePool = 7        // persistent sphere tracing: a workgroup's ray slots refilled from a pool
 };
 
 struct FwdArgs {
@@ -43,6 +44,8 @@ struct FwdArgs {
   int32_t* steps;         // may be null
   int step;               // 0-based step index
   float hit_eps, t_max;
+  int max_steps;          // pool mode: evaluations per ray at most
+  unsigned long long* pool;  // pool mode: rays handed out so far (starts at 0)
   // calib mode: per hidden layer, the max post-ReLU value as ordered uint bits
   unsigned int* amax;
 };
@@ -79,10 +82,13 @@ __device__ void encode_tile(const FwdArgs& a, int64_t ray0, E* X) {
     const int64_t g = ray0 + r;
     float v = 0.f;
     if (g < a.n) {
-      if (MODE == kModeTrace) {
+      if (MODE == kModeTrace || MODE == kModePool) {
+        // the active list (trace) or the workgroup's slots (pool; -1 = empty slot, zeros)
         const int32_t src = a.idx[g];
-        const float tt = a.t_state[src];
-        v = fmaf(tt, a.in[(int64_t)(3 + j) * a.stride + src], a.in[(int64_t)j * a.stride + src]);
+        if (MODE == kModeTrace || src >= 0) {
+          const float tt = a.t_state[src];
+          v = fmaf(tt, a.in[(int64_t)(3 + j) * a.stride + src], a.in[(int64_t)j * a.stride + src]);
+        }
       } else {
         v = a.in[(int64_t)j * a.stride + g];
       }
@@ -139,6 +145,7 @@ __device__ void load_tile(const FwdArgs& a, int64_t ray0, E* X) {
 
 hipError_t launch_forward(const ddf_net_desc& d, const FwdArgs& a, int64_t n_items,
                           hipStream_t st);
+hipError_t launch_pool_trace(const ddf_net_desc& d, const FwdArgs& a, int n_wg, hipStream_t st);
 hipError_t launch_forward8(const ddf_net_desc& d, const FwdArgs& a, int64_t n_items,
                            hipStream_t st);
 

@@ -262,6 +262,131 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
   }
 }
 
+// Persistent sphere tracing (the lane-refill form of the baseline, Sec. IV-D): a grid of one
+// workgroup per CU, each owning the M ray slots of one tile for the whole trace.  Per
+// iteration a workgroup refills its empty slots from the pool (one atomic per workgroup),
+// evaluates the SDF network at p = x + t d for every slot (an empty slot computes on zeros and
+// is ignored), and advances each ray by the same rule as the step-synchronous trace: |s| <
+// hit_eps is a hit (t kept), else t += s, and the ray leaves its slot once t > t_max or after
+// max_steps evaluations.  A ray's evaluation does not depend on which slot or tile holds it,
+// so t, hit and steps equal the step-synchronous trace's bit for bit.  Every workgroup leaves
+// the loop when the pool is exhausted and its slots are empty, so the grid always drains.
+template <class P, int WIDTH, int WAVES>
+__global__ __launch_bounds__(WAVES * 64, 1) void pool_trace_kernel(FwdArgs a) {
+  using C = Chain<P, WIDTH, WAVES>;
+  using E = typename P::E;
+  constexpr int M = C::M, NT = C::NT, LDX = C::LDX;
+  __shared__ __attribute__((aligned(16))) E X[C::XSIZE];
+  __shared__ float headp[WAVES][M][2];
+  __shared__ __attribute__((aligned(16))) float bsm[WIDTH];
+  __shared__ int32_t slot[M];        // ray held by each slot, -1 = empty
+  __shared__ int32_t slot_steps[M];  // evaluations that ray has had
+  __shared__ int32_t live;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nt0 = wave * NT;
+  const float* bias_all = reinterpret_cast<const float*>(a.packed + a.lay.b_off);
+  const float* hb = reinterpret_cast<const float*>(a.packed + a.lay.head_b_off);
+  for (int r = threadIdx.x; r < M; r += WAVES * 64) slot[r] = -1;
+  FwdArgs aa = a;
+  aa.idx = slot;
+  aa.n = M;
+  typename C::Ring ring;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int empty = 0;
+      for (int r = 0; r < M; ++r) empty += slot[r] < 0;
+      // past the end of the pool nothing is claimed, so the counter stays below n + M x grid
+      const unsigned long long seen = __hip_atomic_load(a.pool, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int64_t next = (empty && seen < (unsigned long long)a.n) ? (int64_t)atomicAdd(a.pool, (unsigned long long)empty)
+                                                              : a.n;
+      int n_live = 0;
+      for (int r = 0; r < M; ++r) {
+        if (slot[r] < 0 && next < a.n) {
+          slot[r] = (int32_t)next++;
+          slot_steps[r] = 0;
+        }
+        n_live += slot[r] >= 0;
+      }
+      live = n_live;
+    }
+    __syncthreads();
+    if (live == 0) break;   // uniform: the pool is exhausted and every slot is empty
+    encode_tile<E, M, LDX, kModePool>(aa, 0, X);
+    __syncthreads();
+    for (int l = 0; l < a.n_hidden; ++l) {
+      const int K = l == 0 ? a.lay.k1 : WIDTH;
+      const void* W = a.packed + a.lay.w_off[l];
+      f32x16 acc[C::RT][NT];
+#pragma unroll
+      for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
+      constexpr int kNW = WIDTH / WAVES;
+      constexpr int kBL = (kNW + 63) / 64;
+      float bv[kBL];
+      const float* bl = bias_all + (int64_t)l * WIDTH + nt0 * 32;
+#pragma unroll
+      for (int j = 0; j < kBL; ++j)
+        if (j * 64 + lane < kNW) bv[j] = bl[j * 64 + lane];
+      if (l == 0) {
+        C::preload(ring, W, K / P::KBLK, nt0, lane);
+        C::template gemm<0, true>(acc, X, W, K / P::KBLK, nt0, lane, ring);
+      } else {
+        C::template gemm<WIDTH / P::KBLK, true>(acc, X, W, K / P::KBLK, nt0, lane, ring);
+      }
+#pragma unroll
+      for (int j = 0; j < kBL; ++j)
+        if (j * 64 + lane < kNW) bsm[nt0 * 32 + j * 64 + lane] = bv[j];
+      if (l + 1 < a.n_hidden) C::preload(ring, a.packed + a.lay.w_off[l + 1], WIDTH / P::KBLK, nt0, lane);
+      __syncthreads();
+      epilogue_t<P, WIDTH, kModePool, WAVES>(a, acc, X, headp, bsm, l, 0, M, nt0, lane, wave);
+    }
+    for (int r = threadIdx.x; r < M; r += WAVES * 64) {
+      const int32_t id = slot[r];
+      if (id < 0) continue;
+      float z0 = hb[0];
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) z0 += headp[w][r][0];
+      const int st = slot_steps[r] + 1;
+      slot_steps[r] = st;
+      if (a.steps) a.steps[id] = st;
+      if (fabsf(z0) < a.hit_eps) {
+        a.hit[id] = 1;
+        slot[r] = -1;
+        continue;
+      }
+      const float tn = a.t_state[id] + z0;
+      a.t_state[id] = tn;
+      if (tn > a.t_max || st >= a.max_steps) slot[r] = -1;
+    }
+  }
+}
+
+hipError_t launch_pool_trace(const ddf_net_desc& d, const FwdArgs& a, int n_wg, hipStream_t st) {
+  const dim3 grid((unsigned)n_wg), block(8 * 64);
+  if (d.precision == DDF_FP32) {
+    switch (d.width) {
+      case 256: hipLaunchKernelGGL((pool_trace_kernel<PF32, 256, 8>), grid, block, 0, st, a); break;
+      case 512: hipLaunchKernelGGL((pool_trace_kernel<PF32, 512, 8>), grid, block, 0, st, a); break;
+      case 1024: hipLaunchKernelGGL((pool_trace_kernel<PF32, 1024, 8>), grid, block, 0, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else if (d.precision == DDF_BF16) {
+    switch (d.width) {
+      case 256: hipLaunchKernelGGL((pool_trace_kernel<PBF16, 256, 8>), grid, block, 0, st, a); break;
+      case 512: hipLaunchKernelGGL((pool_trace_kernel<PBF16, 512, 8>), grid, block, 0, st, a); break;
+      case 1024: hipLaunchKernelGGL((pool_trace_kernel<PBF16, 1024, 8>), grid, block, 0, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // 8 waves (two per SIMD, 128 neurons each) when the width allows it, so that one wave's
 // matrix products cover the other's load and LDS latencies.
 template <class P, int WIDTH>

@@ -73,6 +73,8 @@ SIGNATURES = {
     "sdf_trace_workspace_bytes": (_SZ, [_I64]),
     "sdf_sphere_trace": (ctypes.c_int, [_D, _P, _P, _I64, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                         _P, _P, _P, _P, _SZ, _P]),
+    "sdf_sphere_trace_pool": (ctypes.c_int, [_D, _P, _P, _I64, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                             _P, _P, _P, _P, _SZ, _P]),
     "sdf_eval": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P]),
     "ddf_query_hidden": (ctypes.c_int, [_D, _P, _P, _I64, _P, _P]),
     "ddf_train_kept_activation": (ctypes.c_int, [_D, _I64, ctypes.c_int32, _P, _SZ, ctypes.c_int32, _P, _P]),
@@ -239,8 +241,9 @@ def sdf_eval(desc, precision, packed, points):
     return s
 
 
-def sphere_trace(desc, precision, packed, rays, max_steps=128, hit_eps=1e-4, t_max=6.0, ws=None):
-    """(t, hit, steps) of sphere tracing the SDF net along float32 SoA rays [6, n]."""
+def sphere_trace(desc, precision, packed, rays, max_steps=128, hit_eps=1e-4, t_max=6.0, ws=None, pool=False):
+    """(t, hit, steps) of sphere tracing the SDF net along float32 SoA rays [6, n]; pool=True:
+    the persistent lane-refill trace (one launch), else the step-synchronous one."""
     d = desc_c(desc, precision)
     _dev(rays, torch.float32, "rays")
     n = rays.shape[1]
@@ -248,12 +251,12 @@ def sphere_trace(desc, precision, packed, rays, max_steps=128, hit_eps=1e-4, t_m
     t = torch.empty(n, dtype=torch.float32, device=dev)
     hit = torch.empty(n, dtype=torch.uint8, device=dev)
     steps = torch.empty(n, dtype=torch.int32, device=dev)
-    wsb = int(lib().sdf_trace_workspace_bytes(n))
+    wsb = 256 if pool else int(lib().sdf_trace_workspace_bytes(n))
     if ws is None:
         ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=dev)
-    _check(lib().sdf_sphere_trace(ctypes.byref(d), _ptr(packed), _ptr(rays), n, int(max_steps),
-                                  float(hit_eps), float(t_max), _ptr(t), _ptr(hit), _ptr(steps),
-                                  _ptr(ws), ws.numel(), _stream()))
+    fn = lib().sdf_sphere_trace_pool if pool else lib().sdf_sphere_trace
+    _check(fn(ctypes.byref(d), _ptr(packed), _ptr(rays), n, int(max_steps), float(hit_eps), float(t_max), _ptr(t),
+              _ptr(hit), _ptr(steps), _ptr(ws), ws.numel(), _stream()))
     return t, hit, steps
 
 

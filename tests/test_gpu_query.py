@@ -191,6 +191,56 @@ def test_sphere_trace_bf16_planted_box(desc):
     assert np.all(np.abs(box_sdf(p, half)) < 2e-2)
 
 
+def _trace_rays(half, n, seed):
+    rng = np.random.default_rng(seed)
+    o = rng.uniform(-1.5, 1.5, (4 * n + 64, 3))
+    o = o[np.max(np.abs(o) - half, axis=1) > 0.05][:n]
+    aim = rng.uniform(-0.2, 0.2, (len(o), 3))
+    d = np.where(rng.uniform(size=(len(o), 1)) < 0.7, aim - o, rng.standard_normal((len(o), 3)))
+    return I._soa(o, d)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("desc", [I.NetDesc(3, 10, 6, 256, 1), I.NET_SDF], ids=["6x256", "12x1024"])
+def test_pool_trace_equals_step_trace(desc, precision):
+    """The persistent lane-refill trace against the step-synchronous one, bit for bit (t, hit,
+    steps): a planted box SDF (rays converge in a few steps) and a random SDF net (many rays use
+    every step, or leave the box), several batch sizes including one ray, a ragged tail and a
+    batch larger than one tile per CU, and a ray with a NaN origin coordinate."""
+    dev = cuda()
+    half = [0.3, 0.5, 0.7]
+    nets = {"planted": planted_box_sdf(desc, half, 7), "random": I.test_params(desc, 9)}
+    for name, params in nets.items():
+        packed = ddf.pack(desc, precision, _t(params, dev))
+        for n in (1, 33, 64 * 5 + 3, 20000):
+            rays = _trace_rays(half, n, 3 + n)
+            if n > 40:
+                rays[0, 17] = np.nan
+            r = _t(rays, dev)
+            for max_steps, eps in ((128, 1e-4), (7, 1e-2)):
+                a = ddf.sphere_trace(desc, precision, packed, r, max_steps=max_steps, hit_eps=eps, t_max=6.0)
+                b = ddf.sphere_trace(desc, precision, packed, r, max_steps=max_steps, hit_eps=eps, t_max=6.0,
+                                     pool=True)
+                torch.cuda.synchronize()
+                ta, ha, sa = (x.cpu().numpy() for x in a)
+                tb, hb, sb = (x.cpu().numpy() for x in b)
+                assert np.array_equal(ha, hb) and np.array_equal(sa, sb), (name, n, max_steps)
+                assert np.array_equal(ta.view(np.int32), tb.view(np.int32)), (name, n, max_steps)
+            print(f"pool trace {name} {precision}: hits {hb.mean():.2f}, steps mean {sb.mean():.1f}, "
+                  f"at the step limit {(sb == max_steps).mean():.2f}")
+
+
+def test_pool_trace_argument_errors():
+    dev = cuda()
+    desc = I.NetDesc(3, 10, 6, 256, 1)
+    packed = ddf.pack(desc, "fp32", _t(I.test_params(desc, 9), dev))
+    r = torch.zeros((6, 8), device=dev)
+    with pytest.raises(ddf.DDFError, match="max_steps"):
+        ddf.sphere_trace(desc, "fp32", packed, r, max_steps=0, pool=True)
+    with pytest.raises(ddf.DDFError, match="256 bytes"):
+        ddf.sphere_trace(desc, "fp32", packed, r, pool=True, ws=torch.empty(128, dtype=torch.uint8, device=dev))
+
+
 def _calib_rays():
     return I.free_rays(I.scene_mixed(256, 2), 4096, 21)
 
