@@ -156,6 +156,27 @@ template <class E> using V4 = typename V4T<E>::type;
 // Row of the 32x32 accumulator held in register v by `lane`.
 __device__ inline int acc_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
 
+// The accumulator layout holds, for one neuron, 4 consecutive rays of an 8-ray block per lane:
+// rays 0-3 in lanes below 32, rays 4-7 in the others.  Two such blocks q, q + 1 (4 bf16 each)
+// become whole blocks by one lane-half swap per dword: afterwards a lane below 32 holds block
+// q's 8 rays and the others block q + 1's, the 16 contiguous bytes of one [rows / 8][cols][8]
+// store entry (one full-width store per lane instead of two half-filled ones).
+__device__ inline i32x4 pair_blocks(bf16x4 blk_q, bf16x4 blk_q1) {
+  const i32x2 a = __builtin_bit_cast(i32x2, blk_q), b = __builtin_bit_cast(i32x2, blk_q1);
+  const auto s0 = __builtin_amdgcn_permlane32_swap(a[0], b[0], false, false);
+  const auto s1 = __builtin_amdgcn_permlane32_swap(a[1], b[1], false, false);
+  return i32x4{(int)s0[0], (int)s1[0], (int)s0[1], (int)s1[1]};
+}
+
+// The inverse: a lane below 32 loaded block q's 8 rays, the others block q + 1's; returns the
+// lane's 4 rays of block q (first) and of block q + 1 (second) in the accumulator layout.
+__device__ inline void unpair_blocks(i32x4 c, bf16x4& blk_q, bf16x4& blk_q1) {
+  const auto s0 = __builtin_amdgcn_permlane32_swap(c[0], c[2], false, false);
+  const auto s1 = __builtin_amdgcn_permlane32_swap(c[1], c[3], false, false);
+  blk_q = __builtin_bit_cast(bf16x4, i32x2{(int)s0[0], (int)s1[0]});
+  blk_q1 = __builtin_bit_cast(bf16x4, i32x2{(int)s0[1], (int)s1[1]});
+}
+
 // Activation store layout [rows / 8][cols][8]: element (ray g, column c).
 __device__ inline int64_t act_index(int64_t g, int c, int cols) { return ((g >> 3) * cols + c) * 8 + (g & 7); }
 

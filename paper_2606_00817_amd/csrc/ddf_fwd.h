@@ -5,6 +5,14 @@
 
 namespace ddf {
 
+// The bf16 chain with 8 waves writes the ReLU masks of its training forward as bits, which the
+// backward chain's epilogue reads instead of the kept activations.
+template <class P, int WAVES>
+constexpr bool kSpreadStores = sizeof(typename P::E) == 2 && WAVES == 8;
+
+// Mask-bit dwords per lane and layer of the bf16 8-wave chain (RT x NT x 16 bits).
+inline __host__ __device__ int mask_dwords(int width) { return 2 * (width / 32 / 8) * 16 / 32; }
+
 enum FwdMode {
   kModeQuery = 0,   // t = softplus(z_t), xi = sigmoid(z_xi)
   kModeTrain = 1,   // raw logits + activations kept for the backward pass
@@ -34,6 +42,10 @@ struct FwdArgs {
   // mode reads its input tile from hst[l_begin].
   void* hst[kMaxLayers + 1];
   int64_t act_rows;
+  // train / recompute modes of the bf16 8-wave chain: the ReLU masks of H_1..H_n as bits,
+  // [n + 1][tiles][waves][dwords][64 lanes] (slot l for H_l), in the backward epilogue's
+  // register order; null = not written
+  uint32_t* mbits;
   // trace mode
   const int32_t* idx;     // active rays of this step
   const int32_t* count;   // number of active rays

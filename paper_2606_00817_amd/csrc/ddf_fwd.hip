@@ -170,6 +170,21 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
     const float* bias = bias_all + (int64_t)l * WIDTH;
     const bool last = (l + 1 == a.n_hidden);
     E* slab = reinterpret_cast<E*>(a.hst[l + 1]);   // H_(l+1) store, or null: not kept
+    constexpr int kMD = (RT * NT * 16 + 31) / 32;   // mask-bit dwords per lane
+    uint32_t* mw = nullptr;
+    if (kSpreadStores<P, WAVES> && a.mbits)
+      mw = a.mbits + ((((int64_t)(l + 1) * gridDim.x + blockIdx.x) * WAVES + wave) * kMD) * 64 + lane;
+    uint32_t mb[kMD] = {};   // bit (rt NT + t) 16 + v: stored as soon as a dword is complete
+    // every global load of the epilogue is issued before its first store (a load queued behind
+    // stores waits for them as well)
+    float bvs[NT], w0s[NT], w1s[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int n = (nt0 + t) * 32 + (lane & 31);
+      bvs[t] = bias[n];
+      w0s[t] = last ? hw[n] : 0.f;
+      w1s[t] = last && a.n_out > 1 ? hw[WIDTH + n] : 0.f;
+    }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       float hp0[16], hp1[16];
@@ -178,12 +193,19 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int n = (nt0 + t) * 32 + (lane & 31);
-        const float bv = bias[n];
+        const float bv = bvs[t];
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[rt][t][v] = fmaxf(acc[rt][t][v] + bv, 0.f);
+        if constexpr (kSpreadStores<P, WAVES>) {
+          uint32_t bits = 0u;
+#pragma unroll
+          for (int v = 0; v < 16; ++v) bits |= (acc[rt][t][v] > 0.f ? 1u : 0u) << v;
+          const int p = (rt * NT + t) * 16;
+          mb[p >> 5] |= bits << (p & 31);
+        }
         if (last) {
-          const float w0 = hw[n];
-          const float w1 = a.n_out > 1 ? hw[WIDTH + n] : 0.f;
+          const float w0 = w0s[t];
+          const float w1 = w1s[t];
 #pragma unroll
           for (int v = 0; v < 16; ++v) {
             hp0[v] = fmaf(w0, acc[rt][t][v], hp0[v]);
@@ -202,16 +224,43 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
           }
         }
         if (slab) {
+          if constexpr (sizeof(E) == 2) {
+            // blocks q, q + 1 paired across the lane halves: one 16-byte store per lane each
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int64_t g0 = ray0 + rt * 32 + 8 * q;   // 8-ray block of registers 4q..4q+3
-            V4<E> hv;
+            for (int q = 0; q < 4; q += 2) {
+              bf16x4 h0, h1;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) hv[i] = (E)acc[rt][t][4 * q + i];
-            *reinterpret_cast<V4<E>*>(slab + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5)) = hv;
+              for (int i = 0; i < 4; ++i) {
+                h0[i] = (__bf16)acc[rt][t][4 * q + i];
+                h1[i] = (__bf16)acc[rt][t][4 * q + 4 + i];
+              }
+              const i32x4 w = pair_blocks(h0, h1);
+              const int64_t g0 = ray0 + rt * 32 + 8 * (q + (lane >> 5));
+              __builtin_nontemporal_store(w, reinterpret_cast<i32x4*>(slab + ((g0 >> 3) * WIDTH + n) * 8));
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int64_t g0 = ray0 + rt * 32 + 8 * q;   // 8-ray block of registers 4q..4q+3
+              V4<E> hv;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) hv[i] = (E)acc[rt][t][4 * q + i];
+              *reinterpret_cast<V4<E>*>(slab + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5)) = hv;
+            }
           }
         }
         __builtin_amdgcn_sched_barrier(0);   // keep the epilogue tile by tile (no hoisting)
+      }
+      if constexpr (kSpreadStores<P, WAVES>) {
+        if (mw) {
+          if constexpr (NT >= 2) {
+#pragma unroll
+            for (int jj = 0; jj < NT / 2; ++jj) mw[(rt * (NT / 2) + jj) * 64] = mb[rt * (NT / 2) + jj];
+          } else if (rt == RT - 1) {
+#pragma unroll
+            for (int jj = 0; jj < kMD; ++jj) mw[jj * 64] = mb[jj];
+          }
+        }
       }
       if (last) {
 #pragma unroll

@@ -33,6 +33,7 @@ struct TrainWs {
   int64_t headp;            // head-gradient partials [kHeadChunks][2][width + 2]
   int64_t grad;             // fp32 [P] (used when the caller passes no gradient buffer)
   int64_t dwpart;           // fp32 [8][P] weight-gradient partial sums of the ray ranges
+  int64_t mbits;            // ReLU mask bits [n + 1][R / 64][8][dwords][64] (bf16 8-wave chain), or -1
   int64_t total;
   int esize;
 };
@@ -65,6 +66,12 @@ inline TrainWs train_ws(const ddf_net_desc& d, int64_t batch, size_t nparams, in
   w.headp = off; off = align256(off + 4ll * kHeadChunks * 2 * (d.width + 2));
   w.grad = off; off = align256(off + 4 * (int64_t)nparams);
   w.dwpart = off; off = align256(off + 32 * (int64_t)nparams);
+  if (d.precision == DDF_BF16 && d.width >= 256) {
+    w.mbits = off;
+    off = align256(off + 4ll * (n + 1) * (w.R / 64) * 8 * mask_dwords(d.width) * 64);
+  } else {
+    w.mbits = -1;
+  }
   w.total = off;
   return w;
 }
@@ -77,12 +84,14 @@ struct TrainPtrs {
   uint8_t* h[kMaxLayers + 1];
   uint8_t* dl[kMaxLayers + 1];
   bool kept[kMaxLayers + 1];   // written by the training forward pass
+  uint32_t* mbits;             // ReLU mask bits, or null
 };
 
 inline TrainPtrs train_ptrs(const ddf_net_desc& d, const TrainWs& w, uint8_t* ws) {
   TrainPtrs p{};
   const int n = d.n_hidden;
   const int64_t S = (int64_t)d.width * w.R * w.esize;
+  p.mbits = w.mbits >= 0 ? reinterpret_cast<uint32_t*>(ws + w.mbits) : nullptr;
   p.h[0] = ws + w.feat;
   p.kept[0] = true;
   for (int l = 1; l <= n; ++l) {
@@ -287,6 +296,7 @@ struct BwdArgs {
   int lo, hi;                      // this launch computes delta_hi .. delta_lo (1-based)
   const float* dzt;
   const float* dzx;
+  const uint32_t* mbits;           // the forward's ReLU mask bits (bf16 8-wave chain)
 };
 
 // delta_n = (dz_t w_t + dz_xi w_xi) * 1[H_n > 0]; delta_(l) = (delta_(l+1) W_(l+1)) *
@@ -335,6 +345,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
   typename C::Ring ring;
   if (top >= a.lo) C::preload(ring, a.packed + a.lay.wt_off[top], WIDTH / P::KBLK, nt0, lane);
   __syncthreads();
+  constexpr int kMD = (RT * NT * 16 + 31) / 32;   // mask-bit dwords per lane
   for (int l = top; l >= a.lo; --l) {
     f32x16 acc[RT][NT];
 #pragma unroll
@@ -342,6 +353,13 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) acc[rt][t] = f32x16{};
     C::template gemm<WIDTH / P::KBLK>(acc, X, a.packed + a.lay.wt_off[l], WIDTH / P::KBLK, nt0, lane, ring);
+    // the masks of delta_l as the forward's bits, issued before the barrier
+    uint32_t mb[kMD];
+    if constexpr (kSpreadStores<P, WAVES>) {
+      const uint32_t* mw = a.mbits + ((((int64_t)l * gridDim.x + blockIdx.x) * WAVES + wave) * kMD) * 64 + lane;
+#pragma unroll
+      for (int j = 0; j < kMD; ++j) mb[j] = mw[j * 64];
+    }
     if (l > a.lo) C::preload(ring, a.packed + a.lay.wt_off[l - 1], WIDTH / P::KBLK, nt0, lane);
     __syncthreads();
     const E* Hm = reinterpret_cast<const E*>(a.h[l]);   // H_l: the mask of delta_l
@@ -351,25 +369,69 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
       const int n = (nt0 + t) * 32 + (lane & 31);
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        // 4 consecutive rays per register group are contiguous in the store: one vector each
-        V4<E> hm[4];
+        if constexpr (kSpreadStores<P, WAVES>) {
+          const int p = (rt * NT + t) * 16;
+          const uint32_t bits = mb[p >> 5] >> (p & 31);
+          bf16x4 d[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t g0 = ray0 + rt * 32 + 8 * q;
-          hm[q] = *reinterpret_cast<const V4<E>*>(Hm + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5));
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t g0 = ray0 + rt * 32 + 8 * q;
-          V4<E> dv;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int v = 4 * q + i;
-            const float d = (float)hm[q][i] > 0.f ? acc[rt][t][v] : 0.f;
-            dv[i] = (E)d;
-            X[(rt * 32 + acc_row(v, lane)) * LDX + n] = dv[i];
+          for (int v = 0; v < 16; ++v) {
+            d[v >> 2][v & 3] = (__bf16)(((bits >> v) & 1u) ? acc[rt][t][v] : 0.f);
+            X[(rt * 32 + acc_row(v, lane)) * LDX + n] = d[v >> 2][v & 3];
           }
-          *reinterpret_cast<V4<E>*>(Dm + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5)) = dv;
+          {
+#pragma unroll
+            for (int q = 0; q < 4; q += 2) {
+              const i32x4 w = pair_blocks(d[q], d[q + 1]);
+              const int64_t g0 = ray0 + rt * 32 + 8 * (q + (lane >> 5));
+              __builtin_nontemporal_store(w, reinterpret_cast<i32x4*>(Dm + ((g0 >> 3) * WIDTH + n) * 8));
+            }
+          }
+        } else if constexpr (sizeof(E) == 2) {
+          // whole 8-ray blocks of the stores, paired across the lane halves: a lane below 32
+          // loads / stores block q, the others block q + 1 (16 bytes each)
+          i32x4 hc[2];
+#pragma unroll
+          for (int qq = 0; qq < 2; ++qq) {
+            const int64_t g0 = ray0 + rt * 32 + 8 * (2 * qq + (lane >> 5));
+            hc[qq] = *reinterpret_cast<const i32x4*>(Hm + ((g0 >> 3) * WIDTH + n) * 8);
+          }
+#pragma unroll
+          for (int qq = 0; qq < 2; ++qq) {
+            bf16x4 hm0, hm1, d0, d1;
+            unpair_blocks(hc[qq], hm0, hm1);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int v0 = 8 * qq + i, v1 = 8 * qq + 4 + i;
+              d0[i] = (__bf16)((float)hm0[i] > 0.f ? acc[rt][t][v0] : 0.f);
+              d1[i] = (__bf16)((float)hm1[i] > 0.f ? acc[rt][t][v1] : 0.f);
+              X[(rt * 32 + acc_row(v0, lane)) * LDX + n] = d0[i];
+              X[(rt * 32 + acc_row(v1, lane)) * LDX + n] = d1[i];
+            }
+            const i32x4 w = pair_blocks(d0, d1);
+            const int64_t g0 = ray0 + rt * 32 + 8 * (2 * qq + (lane >> 5));
+            __builtin_nontemporal_store(w, reinterpret_cast<i32x4*>(Dm + ((g0 >> 3) * WIDTH + n) * 8));
+          }
+        } else {
+          // 4 consecutive rays per register group are contiguous in the store: one vector each
+          V4<E> hm[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t g0 = ray0 + rt * 32 + 8 * q;
+            hm[q] = *reinterpret_cast<const V4<E>*>(Hm + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5));
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int64_t g0 = ray0 + rt * 32 + 8 * q;
+            V4<E> dv;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int v = 4 * q + i;
+              const float d = (float)hm[q][i] > 0.f ? acc[rt][t][v] : 0.f;
+              dv[i] = (E)d;
+              X[(rt * 32 + acc_row(v, lane)) * LDX + n] = dv[i];
+            }
+            *reinterpret_cast<V4<E>*>(Dm + ((g0 >> 3) * WIDTH + n) * 8 + 4 * (lane >> 5)) = dv;
+          }
         }
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -783,6 +845,7 @@ static int run_forward_rows(const ddf_net_desc& d, const void* packed, const flo
   for (int l = 1; l <= d.n_hidden; ++l)
     a.hst[l] = full ? (p.kept[l] ? p.h[l] : nullptr) : (l > l_begin && l <= l_end ? p.h[l] : nullptr);
   if (l_begin > 0) a.hst[l_begin] = p.h[l_begin];   // the recomputation's input
+  a.mbits = p.mbits;
   return hip_status(launch_forward(d, a, w.R, st), "training forward launch");
 }
 
@@ -811,6 +874,7 @@ static int run_backward(const ddf_net_desc& d, const void* packed, const float* 
     for (int l = 0; l <= nh; ++l) { b.h[l] = p.h[l]; b.dl[l] = p.dl[l]; }
     b.lo = lo; b.hi = hi;
     b.dzt = dzt; b.dzx = dzx;
+    b.mbits = p.mbits;
     e = d.precision == DDF_FP32 ? launch_bwd<PF32>(d, b, st) : launch_bwd<PBF16>(d, b, st);
     if (e != hipSuccess) return hip_status(e, "backward chain launch");
     DwArgs a{};
