@@ -71,9 +71,15 @@ __global__ void finish_scales_kernel(PackArgs a) {
   s[4 * l + kQuantNext] = qn;
 }
 
-// One thread per (block, lane): writes that lane's kblk/2 elements of one layer.
-__global__ void pack_layer_kernel(PackArgs a, int l, int transposed) {
+// One thread per (block, lane): writes that lane's kblk/2 elements (16 or 32 bytes) of one
+// layer.  blockIdx.y selects the job: layer j, or (j >= n_hidden) the transposed copy of layer
+// j - n_hidden + 1; every layer of a repack in one launch.
+__global__ void pack_layer_kernel(PackArgs a, int with_transposed) {
   const Geo g = geo_of(a.precision);
+  const int job = blockIdx.y;
+  const int transposed = job >= a.n_hidden ? 1 : 0;
+  const int l = transposed ? job - a.n_hidden + 1 : job;
+  if (transposed && !with_transposed) return;
   const bool first = (l == 0);
   const int kblk = first ? g.kblk1 : g.kblk;
   const int eb = first ? g.elem1_bytes : g.elem_bytes;
@@ -96,6 +102,10 @@ __global__ void pack_layer_kernel(PackArgs a, int l, int transposed) {
     const float* s = reinterpret_cast<const float*>(a.packed + a.lay.scale_off);
     qs = 1.f / s[4 * l + kScaleW];     // exact: a power of two
   }
+  // the lane's bytes are gathered in registers and leave as 16-byte stores (per * eb is 16
+  // or 32: fp32 8 x 4, bf16 8 x 2, e4m3 32 x 1, layer-1 bf16 8 x 2)
+  i32x4 out[2] = {};
+  uint8_t* ob = reinterpret_cast<uint8_t*>(out);
   for (int j = 0; j < per; ++j) {
     int k = kbase + j;
     float w;
@@ -106,15 +116,17 @@ __global__ void pack_layer_kernel(PackArgs a, int l, int transposed) {
       w = transposed ? W[(int64_t)k * fan_in + n] : W[(int64_t)n * fan_in + k];
     }
     if (eb == 4) {
-      reinterpret_cast<float*>(dst)[j] = w;
+      reinterpret_cast<float*>(ob)[j] = w;
     } else if (eb == 2) {
-      reinterpret_cast<__bf16*>(dst)[j] = to_bf16(w);
+      reinterpret_cast<__bf16*>(ob)[j] = to_bf16(w);
     } else {
       float q = fp8_quant(w * qs);
       int pk = __builtin_amdgcn_cvt_pk_fp8_f32(q, q, 0, false);
-      dst[j] = (uint8_t)(pk & 0xff);
+      ob[j] = (uint8_t)(pk & 0xff);
     }
   }
+  reinterpret_cast<i32x4*>(dst)[0] = out[0];
+  if (per * eb > 16) reinterpret_cast<i32x4*>(dst)[1] = out[1];
 }
 
 __global__ void pack_small_kernel(PackArgs a) {
@@ -156,15 +168,19 @@ hipError_t launch_pack(const ddf_net_desc& d, const float* master, const float* 
   if (d.precision == DDF_FP8_E4M3 && d.n_hidden > 1)
     amax_kernel<<<dim3(64, d.n_hidden - 1), kThreads, 0, st>>>(a);
   finish_scales_kernel<<<1, 64, 0, st>>>(a);
-  for (int l = 0; l < d.n_hidden; ++l) {
+  {
+    // one launch: jobs 0 .. n_hidden - 1 the layers, then the transposed copies of layers 2..n
     const Geo g = geo_of(d.precision);
-    int K = l == 0 ? a.lay.k1 : d.width;
-    int kblk = l == 0 ? g.kblk1 : g.kblk;
-    int64_t lanes = (int64_t)(d.width / 32) * (K / kblk) * 64;
-    int blocks = (int)((lanes + kThreads - 1) / kThreads);
-    pack_layer_kernel<<<blocks, kThreads, 0, st>>>(a, l, 0);
-    if (with_transposed && l >= 1 && d.precision != DDF_FP8_E4M3)
-      pack_layer_kernel<<<blocks, kThreads, 0, st>>>(a, l, 1);
+    int64_t lanes = 0;
+    for (int l = 0; l < d.n_hidden; ++l) {
+      const int K = l == 0 ? a.lay.k1 : d.width;
+      const int kblk = l == 0 ? g.kblk1 : g.kblk;
+      const int64_t ll = (int64_t)(d.width / 32) * (K / kblk) * 64;
+      lanes = ll > lanes ? ll : lanes;
+    }
+    const bool tr = with_transposed && d.precision != DDF_FP8_E4M3 && d.n_hidden > 1;
+    const dim3 grid((unsigned)((lanes + kThreads - 1) / kThreads), (unsigned)(d.n_hidden + (tr ? d.n_hidden - 1 : 0)));
+    pack_layer_kernel<<<grid, kThreads, 0, st>>>(a, tr ? 1 : 0);
   }
   pack_small_kernel<<<256, kThreads, 0, st>>>(a);
   return hipGetLastError();
