@@ -54,7 +54,7 @@ SUBSET = 16                # the float64 oracle answers every 16th ray of the la
 COUNTER_SCALE = {"FETCH_SIZE": 2.0, "WRITE_SIZE": 1.0}
 TRAFFIC_KIB = {
     "bf16": {"FETCH_SIZE": 128417962, "WRITE_SIZE": 131072,
-             "sha256": "70c71fc84c825b2f7cf939a94d013ab7b81714e4b0200fcffedf2b977059d03d"},
+             "sha256": "7ee688c18c852c226494b460dfc1ebced86ccf0ce57f748d5632aa3432231693"},
 }
 KERNEL_SOURCES = {
     "fp32": ["ddf_fwd.hip", "ddf_chain.h", "ddf_fwd.h", "ddf_internal.h"],

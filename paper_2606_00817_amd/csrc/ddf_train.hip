@@ -314,30 +314,48 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
   const int64_t ray0 = (int64_t)blockIdx.x * M;
   const float* hw = reinterpret_cast<const float*>(a.packed + a.lay.head_w_off);
 
+  // The first delta in LDS, one [8 rays] block of one neuron per thread and step (vector
+  // loads and stores of whole blocks of the [R / 8][WIDTH][8] stores).
   int top;   // the first delta the loop computes
   if (a.hi == a.n_hidden) {
     const E* Hn = reinterpret_cast<const E*>(a.h[a.n_hidden]);
     E* Dn = reinterpret_cast<E*>(a.dl[a.n_hidden]);
-    for (int idx = threadIdx.x; idx < M * WIDTH; idx += WAVES * 64) {
-      const int q = idx & 7;
-      const int j = (idx >> 3) % WIDTH;
-      const int rb = (idx >> 3) / WIDTH;
-      const int64_t g = ray0 + rb * 8 + q;
-      const int64_t gi = act_index(g, j, WIDTH);
-      float d = a.dzt[g] * hw[j];
-      if (a.n_out > 1) d = fmaf(a.dzx[g], hw[WIDTH + j], d);
-      d = (float)Hn[gi] > 0.f ? d : 0.f;
-      X[(rb * 8 + q) * LDX + j] = (E)d;
-      Dn[gi] = (E)d;
+    for (int c = threadIdx.x; c < (M / 8) * WIDTH; c += WAVES * 64) {
+      const int rb = c / WIDTH, j = c % WIDTH;
+      const int64_t g0 = ray0 + rb * 8;
+      const int64_t o = ((g0 >> 3) * WIDTH + j) * 8;
+      const V4<E> h0 = *reinterpret_cast<const V4<E>*>(Hn + o);
+      const V4<E> h1 = *reinterpret_cast<const V4<E>*>(Hn + o + 4);
+      const f32x4 t0 = *reinterpret_cast<const f32x4*>(a.dzt + g0);
+      const f32x4 t1 = *reinterpret_cast<const f32x4*>(a.dzt + g0 + 4);
+      f32x4 x0{}, x1{};
+      if (a.n_out > 1) {
+        x0 = *reinterpret_cast<const f32x4*>(a.dzx + g0);
+        x1 = *reinterpret_cast<const f32x4*>(a.dzx + g0 + 4);
+      }
+      const float w0 = hw[j], w1 = a.n_out > 1 ? hw[WIDTH + j] : 0.f;
+      V4<E> d0, d1;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        float d = (q < 4 ? t0[q] : t1[q - 4]) * w0;
+        if (a.n_out > 1) d = fmaf(q < 4 ? x0[q] : x1[q - 4], w1, d);
+        d = (float)(q < 4 ? h0[q] : h1[q - 4]) > 0.f ? d : 0.f;
+        X[(rb * 8 + q) * LDX + j] = (E)d;
+        if (q < 4) d0[q] = (E)d; else d1[q - 4] = (E)d;
+      }
+      *reinterpret_cast<V4<E>*>(Dn + o) = d0;
+      *reinterpret_cast<V4<E>*>(Dn + o + 4) = d1;
     }
     top = a.n_hidden - 1;
   } else {
     const E* Du = reinterpret_cast<const E*>(a.dl[a.hi + 1]);
-    for (int idx = threadIdx.x; idx < M * WIDTH; idx += WAVES * 64) {
-      const int q = idx & 7;
-      const int c = (idx >> 3) % WIDTH;
-      const int rb = (idx >> 3) / WIDTH;
-      X[(rb * 8 + q) * LDX + c] = Du[(((ray0 >> 3) + rb) * WIDTH + c) * 8 + q];
+    for (int c = threadIdx.x; c < (M / 8) * WIDTH; c += WAVES * 64) {
+      const int rb = c / WIDTH, j = c % WIDTH;
+      const int64_t o = (((ray0 >> 3) + rb) * WIDTH + j) * 8;
+      const V4<E> u0 = *reinterpret_cast<const V4<E>*>(Du + o);
+      const V4<E> u1 = *reinterpret_cast<const V4<E>*>(Du + o + 4);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) X[(rb * 8 + q) * LDX + j] = q < 4 ? u0[q] : u1[q - 4];
     }
     top = a.hi;
   }
@@ -360,10 +378,18 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
 #pragma unroll
       for (int j = 0; j < kMD; ++j) mb[j] = mw[j * 64];
     }
-    if (l > a.lo) C::preload(ring, a.packed + a.lay.wt_off[l - 1], WIDTH / P::KBLK, nt0, lane);
+    __builtin_amdgcn_sched_barrier(0);
+    // the next layer's first weight blocks; the last layer loads its own blocks again, so that
+    // the preload is unconditional and the wait for the mask bits above leaves it in flight
+    // (behind a branch the wait would also cover the preload)
+    C::preload(ring, a.packed + a.lay.wt_off[l > a.lo ? l - 1 : l], WIDTH / P::KBLK, nt0, lane);
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
     const E* Hm = reinterpret_cast<const E*>(a.h[l]);   // H_l: the mask of delta_l
     E* Dm = reinterpret_cast<E*>(a.dl[l]);
+    // this workgroup's 8-ray blocks of the store (uniform) and the lane's place in a block pair
+    E* const Dw = Dm + (ray0 >> 3) * WIDTH * 8;
+    const uint32_t lane_off = ((uint32_t)(lane >> 5) * WIDTH + nt0 * 32 + (lane & 31)) * 8;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int n = (nt0 + t) * 32 + (lane & 31);
@@ -381,9 +407,11 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
           {
 #pragma unroll
             for (int q = 0; q < 4; q += 2) {
+              // block rt 4 + q (lanes below 32) or rt 4 + q + 1, neuron n: a uniform base plus
+              // the lane's offset
               const i32x4 w = pair_blocks(d[q], d[q + 1]);
-              const int64_t g0 = ray0 + rt * 32 + 8 * (q + (lane >> 5));
-              __builtin_nontemporal_store(w, reinterpret_cast<i32x4*>(Dm + ((g0 >> 3) * WIDTH + n) * 8));
+              E* const blk = Dw + ((rt * 4 + q) * WIDTH + t * 32) * 8;
+              __builtin_nontemporal_store(w, reinterpret_cast<i32x4*>(blk + lane_off));
             }
           }
         } else if constexpr (sizeof(E) == 2) {
