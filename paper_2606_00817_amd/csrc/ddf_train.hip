@@ -314,48 +314,64 @@ __global__ __launch_bounds__(WAVES * 64, 1) void bwd_chain_kernel(BwdArgs a) {
   const int64_t ray0 = (int64_t)blockIdx.x * M;
   const float* hw = reinterpret_cast<const float*>(a.packed + a.lay.head_w_off);
 
-  // The first delta in LDS, one [8 rays] block of one neuron per thread and step (vector
-  // loads and stores of whole blocks of the [R / 8][WIDTH][8] stores).
+  // The first delta in LDS, one [8 rays] block of one neuron per chunk (vector loads and
+  // stores of whole blocks of the [R / 8][WIDTH][8] stores): every load of a thread's chunks
+  // is issued before the first is used, the logit gradients of the tile go through LDS.
+  constexpr int kChunks = (M / 8) * WIDTH / (WAVES * 64);
+  static_assert((M / 8) * WIDTH % (WAVES * 64) == 0, "whole chunks per thread");
+  __shared__ float dzs[2][M];
   int top;   // the first delta the loop computes
   if (a.hi == a.n_hidden) {
     const E* Hn = reinterpret_cast<const E*>(a.h[a.n_hidden]);
     E* Dn = reinterpret_cast<E*>(a.dl[a.n_hidden]);
-    for (int c = threadIdx.x; c < (M / 8) * WIDTH; c += WAVES * 64) {
-      const int rb = c / WIDTH, j = c % WIDTH;
-      const int64_t g0 = ray0 + rb * 8;
-      const int64_t o = ((g0 >> 3) * WIDTH + j) * 8;
-      const V4<E> h0 = *reinterpret_cast<const V4<E>*>(Hn + o);
-      const V4<E> h1 = *reinterpret_cast<const V4<E>*>(Hn + o + 4);
-      const f32x4 t0 = *reinterpret_cast<const f32x4*>(a.dzt + g0);
-      const f32x4 t1 = *reinterpret_cast<const f32x4*>(a.dzt + g0 + 4);
-      f32x4 x0{}, x1{};
-      if (a.n_out > 1) {
-        x0 = *reinterpret_cast<const f32x4*>(a.dzx + g0);
-        x1 = *reinterpret_cast<const f32x4*>(a.dzx + g0 + 4);
-      }
-      const float w0 = hw[j], w1 = a.n_out > 1 ? hw[WIDTH + j] : 0.f;
-      V4<E> d0, d1;
+    for (int r = threadIdx.x; r < M; r += WAVES * 64) {
+      dzs[0][r] = a.dzt[ray0 + r];
+      dzs[1][r] = a.n_out > 1 ? a.dzx[ray0 + r] : 0.f;
+    }
+    V4<E> h[kChunks][2];
+    float w0[kChunks], w1[kChunks];
+#pragma unroll
+    for (int k = 0; k < kChunks; ++k) {
+      const int c = threadIdx.x + k * WAVES * 64, rb = c / WIDTH, j = c % WIDTH;
+      const int64_t o = (((ray0 >> 3) + rb) * WIDTH + j) * 8;
+      h[k][0] = *reinterpret_cast<const V4<E>*>(Hn + o);
+      h[k][1] = *reinterpret_cast<const V4<E>*>(Hn + o + 4);
+      w0[k] = hw[j];
+      w1[k] = a.n_out > 1 ? hw[WIDTH + j] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kChunks; ++k) {
+      const int c = threadIdx.x + k * WAVES * 64, rb = c / WIDTH, j = c % WIDTH;
+      const int64_t o = (((ray0 >> 3) + rb) * WIDTH + j) * 8;
+      V4<E> dv[2];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        float d = (q < 4 ? t0[q] : t1[q - 4]) * w0;
-        if (a.n_out > 1) d = fmaf(q < 4 ? x0[q] : x1[q - 4], w1, d);
-        d = (float)(q < 4 ? h0[q] : h1[q - 4]) > 0.f ? d : 0.f;
+        float d = dzs[0][rb * 8 + q] * w0[k];
+        if (a.n_out > 1) d = fmaf(dzs[1][rb * 8 + q], w1[k], d);
+        d = (float)h[k][q >> 2][q & 3] > 0.f ? d : 0.f;
         X[(rb * 8 + q) * LDX + j] = (E)d;
-        if (q < 4) d0[q] = (E)d; else d1[q - 4] = (E)d;
+        dv[q >> 2][q & 3] = (E)d;
       }
-      *reinterpret_cast<V4<E>*>(Dn + o) = d0;
-      *reinterpret_cast<V4<E>*>(Dn + o + 4) = d1;
+      *reinterpret_cast<V4<E>*>(Dn + o) = dv[0];
+      *reinterpret_cast<V4<E>*>(Dn + o + 4) = dv[1];
     }
     top = a.n_hidden - 1;
   } else {
     const E* Du = reinterpret_cast<const E*>(a.dl[a.hi + 1]);
-    for (int c = threadIdx.x; c < (M / 8) * WIDTH; c += WAVES * 64) {
-      const int rb = c / WIDTH, j = c % WIDTH;
-      const int64_t o = (((ray0 >> 3) + rb) * WIDTH + j) * 8;
-      const V4<E> u0 = *reinterpret_cast<const V4<E>*>(Du + o);
-      const V4<E> u1 = *reinterpret_cast<const V4<E>*>(Du + o + 4);
+    V4<E> u[kChunks][2];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) X[(rb * 8 + q) * LDX + j] = q < 4 ? u0[q] : u1[q - 4];
+    for (int k = 0; k < kChunks; ++k) {
+      const int c = threadIdx.x + k * WAVES * 64, rb = c / WIDTH, j = c % WIDTH;
+      const int64_t o = (((ray0 >> 3) + rb) * WIDTH + j) * 8;
+      u[k][0] = *reinterpret_cast<const V4<E>*>(Du + o);
+      u[k][1] = *reinterpret_cast<const V4<E>*>(Du + o + 4);
+    }
+#pragma unroll
+    for (int k = 0; k < kChunks; ++k) {
+      const int c = threadIdx.x + k * WAVES * 64, rb = c / WIDTH, j = c % WIDTH;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) X[(rb * 8 + q) * LDX + j] = u[k][q >> 2][q & 3];
     }
     top = a.hi;
   }
