@@ -4,8 +4,10 @@ The workloads: 2^20 shadow rays through the 12 x 1024 DDF (the benchmark's launc
 ambient-occlusion batch of 512 x 512 surface points x 32 cosine rays (8,388,608 rays),
 and 2^24 mixed shadow/AO/one-bounce rays through the 16 x 1024 DDF.  Every output is
 checked against properties that hold at any size (finite, t >= 0, 0 <= xi <= 1); a
-strided sample is compared with the float64 oracle (fp32: per-ray rounding-model
-tolerance; bf16: the emulated oracle; fp8: the format's own error)."""
+sample of 2,048 evenly spaced rays plus both sides of 64 seeded 128-ray tile boundaries
+(the workgroup tiles are 32, 64 or 128 rays) and the last ray is compared with the float64
+oracle (fp32: per-ray rounding-model tolerance; bf16: the emulated oracle; fp8: the
+format's own error)."""
 import numpy as np
 import pytest
 import torch
@@ -17,7 +19,7 @@ from tests.helpers import cuda, fp32_forward_sigma, U32
 
 pytestmark = pytest.mark.gpu
 
-SAMPLE = 256
+SAMPLE = 2048
 
 
 def _t(x, dev):
@@ -31,8 +33,9 @@ def _props(t, xi):
 
 def _sample(n):
     idx = np.linspace(0, n - 1, SAMPLE).astype(np.int64)
-    idx[-1] = n - 1                       # the ragged end of the last tile is always checked
-    return idx
+    tiles = np.random.default_rng(7).integers(1, n // 128, 64)
+    edges = np.concatenate([tiles * 128 - 1, tiles * 128])   # the last ray of a tile, the first of the next
+    return np.unique(np.concatenate([idx, edges, [n - 1]]))  # the ragged end of the last tile always
 
 
 def _check_fp32_sample(desc, params, rays_s, t_s, xi_s):
