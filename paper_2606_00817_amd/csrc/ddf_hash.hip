@@ -190,19 +190,6 @@ __device__ __forceinline__ void axpy_row(const float* row, float v, float (&h)[k
   }
 }
 
-// sum_j row[j] v[j].
-__device__ __forceinline__ float dot_row(const float* row, const float (&v)[kHW]) {
-  const f32x4* r4 = reinterpret_cast<const f32x4*>(row);
-  float acc = 0.f;
-#pragma unroll
-  for (int q = 0; q < kHW / 4; ++q) {
-    const f32x4 w4 = r4[q];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) acc = fmaf(w4[e], v[4 * q + e], acc);
-  }
-  return acc;
-}
-
 // The first layer's pre-activation of one ray, fused with the encoding: each input feature
 // is added into h = b1 + W1 g as soon as it exists, so the 64-wide input vector is never held.
 // Features in order: the trilinear lookup of every level (2 each), then the direction code
