@@ -13,7 +13,9 @@ invocation, each query leg with its own roofline and precision statistics:
   * the ambient-occlusion batch: 512 x 512 surface points x 32 cosine rays (8,388,608 rays)
     through the 12 x 1024 DDF in bf16, fp8 and fp32;
   * 2^20 shadow rays through the 12 x 1024 DDF in fp32, bf16 and fp8, and sphere tracing of a
-    signed-distance MLP of the same size along the same rays (the paper's baseline);
+    signed-distance MLP of the same size along the same rays (the paper's baseline) at three
+    hit thresholds and at 1K, 10K and 100K rays, with the float64 oracle's trace of the
+    analytic distance bound on every 128th ray as the yardstick;
   * the bf16 and fp8 queries at 1K, 10K and 100K rays and the tiny 4 x 128 net;
   * distillation training steps (65,536 rays through the 12 x 1024 net; 262,144 rays through
     the 16 x 1024 net with activations recomputed every 4 layers; bf16 and fp32 each);
@@ -229,7 +231,7 @@ def main():
                     help="training steps of the 12 x 1024 field distilled for the distill leg")
     ap.add_argument("--shade-steps", type=int, default=30000,
                     help="recipe steps of the hash-grid field trained for the shade leg")
-    ap.add_argument("--sdf-fit-steps", type=int, default=400,
+    ap.add_argument("--sdf-fit-steps", type=int, default=3000,
                     help="fitting steps of the SDF MLP the trace leg sphere-traces")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -338,9 +340,10 @@ def main():
         out["train_large"] = train_leg(torch, ddf, I, dev, timer, 4, batch=1 << 18, desc=I.NET_LARGE,
                                        recompute_every=4, seed=1300, lr=3e-4)
         progress("train_large leg done")
+    trace_host = None
     if "trace" in legs and shadow is not None:
-        out["sphere_trace"] = trace_leg(torch, ddf, I, dev, shadow.rays, timer, out["shadow_2p20_12x1024"], scene,
-                                        args.sdf_fit_steps)
+        out["sphere_trace"], trace_host = trace_leg(torch, ddf, I, dev, shadow, timer, out["shadow_2p20_12x1024"],
+                                                    scene, args.sdf_fit_steps)
         progress("trace leg done")
     distilled = None
     if "distill" in legs and ao is not None:
@@ -375,6 +378,9 @@ def main():
             if name == "mixed":
                 out.setdefault("precision_stats", {})["vs_float64_subset"] = sub
         progress("oracle subsets done")
+    if "cpu" in legs and trace_host is not None:
+        trace_oracle_stats(scene, trace_host, out["sphere_trace"])
+        progress("trace float64 statistics done")
     if "cpu" in legs and distilled is not None:
         distilled_oracle_stats(I, distilled, ao_np, out["distilled_12x1024"])
         progress("distilled float64 statistics done")
@@ -759,13 +765,16 @@ def shade_leg(torch, ddf, I, dev, timer, steps):
             "paper_table6": {"shadow_psnr_db": 30.3, "ao_psnr_db": 21.3}}
 
 
-def fit_sdf(torch, ddf, I, dev, scene, steps=400, batch=65536, prec="bf16", seed=100):
+def fit_sdf(torch, ddf, I, dev, scene, steps=3000, batch=65536, prec="bf16", seed=100, n_batches=48):
     """Fit the 12 x 1024 signed-distance MLP to the scene's analytic distance bound with the
-    library's own fitting step (L1 on the distance, Adam, cosine-decayed lr)."""
+    library's own fitting step (L1 on the distance, Adam, lr cosine-decayed from 1e-3 to
+    1e-5), cycling through n_batches fixed batches of fitting points (half uniform in the
+    box, half in two bands about the surface).  The default is the distilled DDF's budget:
+    3,000 bf16 steps of 65,536 samples."""
     import math
     desc = I.NET_SDF
     prims = torch.from_numpy(ddf.scene_prims(scene)).to(dev)
-    pool = [torch.from_numpy(I.sdf_train_points(scene, batch, 40 + j)).to(dev) for j in range(8)]
+    pool = [torch.from_numpy(I.sdf_fit_points(scene, batch, 40 + j)).to(dev) for j in range(n_batches)]
     gts = [ddf.scene_sdf(prims, p) for p in pool]
     master = torch.from_numpy(I.he_init(desc, seed)).to(dev)
     m = torch.zeros_like(master)
@@ -774,69 +783,156 @@ def fit_sdf(torch, ddf, I, dev, scene, steps=400, batch=65536, prec="bf16", seed
     ws = torch.empty(ddf.train_workspace_bytes(desc, prec, batch), dtype=torch.uint8, device=dev)
     loss = torch.empty(4, dtype=torch.float32, device=dev)
     flag = torch.empty(4, dtype=torch.int32, device=dev)
-    lr0, lr1 = 3e-4, 3e-5
+    lr0, lr1 = 1e-3, 1e-5
+    t0 = time.perf_counter()
     for s in range(1, steps + 1):
         lr = lr1 + 0.5 * (lr0 - lr1) * (1 + math.cos(math.pi * (s - 1) / steps))
         hp = ddf.TrainHParamsC(lr, 0.9, 0.999, 1e-8, 0.0, 1.0, s)
         j = (s - 1) % len(pool)
         ddf.sdf_train_step(desc, prec, master, m, v, packed, pool[j], gts[j], hp, ws, loss_out=loss, flag=flag)
-    held = torch.from_numpy(I.sdf_train_points(scene, batch, 99)).to(dev)
-    held_gt = ddf.scene_sdf(prims, held)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t0
     packed32 = ddf.pack(desc, "fp32", master)
-    err = (ddf.sdf_eval(desc, "fp32", packed32, held) - held_gt).abs()
-    return (packed32, ddf.pack(desc, "bf16", master)), {"steps": steps, "batch": batch, "precision": prec, "final_loss": float(loss[0].item()),
-                      "heldout_mean_abs_err": float(err.mean().item()),
-                      "heldout_p90_abs_err": float(err.quantile(0.9).item())}
+    fit = {"steps": steps, "batch": batch, "batches": n_batches, "precision": prec, "lr": [lr0, lr1],
+           "fit_s": fit_s, "final_loss": float(loss[0].item())}
+    for name, pts in (("heldout", I.sdf_train_points(scene, batch, 99)),
+                      ("heldout_near_surface", I.sdf_train_points(scene, batch, 98, sigma=0.005))):
+        p = torch.from_numpy(pts).to(dev)
+        err = (ddf.sdf_eval(desc, "fp32", packed32, p) - ddf.scene_sdf(prims, p)).abs()
+        fit[f"{name}_mean_abs_err"] = float(err.mean().item())
+        fit[f"{name}_p90_abs_err"] = float(err.quantile(0.9).item())
+    return (packed32, ddf.pack(desc, "bf16", master)), fit
 
 
-def trace_leg(torch, ddf, I, dev, rays, timer, out, scene, fit_steps=400):
-    """Sphere tracing of a 12 x 1024 signed-distance MLP along the same shadow rays.
+def trace_leg(torch, ddf, I, dev, shadow, timer, out, scene, fit_steps=3000):
+    """Sphere tracing of a 12 x 1024 signed-distance MLP along the shadow leg's rays.
 
     The SDF MLP is fitted to the scene first (fit_sdf).  fp32, at most 128 steps, miss beyond
-    t = 6: the persistent lane-refill trace (one launch) at hit thresholds 1e-2, 1e-3 and 1e-4,
-    each with its unconverged share and its ratio to the DDF query of the same rays; the
-    step-synchronous trace at 1e-4 (same answers bit for bit, its time for comparison); and the
-    bf16 trace at 1e-4 (the same-precision comparison with the bf16 DDF query)."""
+    t = 6: the persistent lane-refill trace (one launch) over 2^20 shadow rays at hit
+    thresholds 1e-2, 1e-3 and 1e-4, each with its unconverged share and its ratio to the DDF
+    query of the shadow leg.  A trace stops wherever |s| < threshold, also at its own origin,
+    so for each threshold the ray origins are lifted max(1e-3, 2 x threshold) off the surface
+    (the same surface points, and the 1e-3 lift of the DDF's rays at 1e-4); the share of rays
+    that stop at their first evaluation is reported.  Then the step-synchronous trace at 1e-4
+    (same answers bit for bit, its time for comparison); the bf16 trace at 1e-4 (the
+    same-precision comparison with the bf16 DDF query); and, as in the paper's table of ray
+    counts (Sec. IV-D, Table IV), the first 1K, 10K and 100K rays traced at 1e-3 and 1e-4
+    against the fp32 and bf16 DDF queries of as many rays.  Rays still running after 128
+    steps at 1e-4 are described by the network's value at their last point and its slope
+    along the ray there (a central difference over +-1e-4): a step t + s converges on a root
+    only where that slope lies in (-2, 0).  Returns the report and, per threshold, every
+    128th ray of the traced set (host float32) for the cpu leg's float64 trace."""
     desc = I.NET_SDF
     (packed, packed_bf16), fit = fit_sdf(torch, ddf, I, dev, scene, steps=fit_steps)
-    n = rays.shape[1]
+    n = shadow.n
     prims = torch.from_numpy(ddf.scene_prims(scene)).to(dev)
-    tg, hg = ddf.cast_targets(prims, rays)
     prec = out   # the shadow leg's query timings on the same rays, per precision
     edges = [1, 2, 4, 8, 16, 32, 64, 128, 129]
+    sets = {}
+    for eps in (1e-2, 1e-3, 1e-4):
+        lift = max(I.NORMAL_OFFSET, 2 * eps)
+        r = shadow.rays if lift == I.NORMAL_OFFSET else torch.from_numpy(I.shadow_rays(scene, n, 12, offset=lift)).to(dev)
+        sets[eps] = (lift, r, ddf.cast_targets(prims, r)[1])
 
-    def stats(ms, res_t):
+    def stuck(rays, hg, t, steps):
+        u = (steps >= 128).nonzero().flatten()
+        if u.numel() == 0:
+            return {}
+        o, d = rays[0:3, u], rays[3:6, u]
+        h = 1e-4
+        ev = lambda tt: ddf.sdf_eval(desc, "fp32", packed, (o + tt[None, :] * d).contiguous())
+        s = ev(t[u])
+        slope = (ev(t[u] + h) - ev(t[u] - h)) / (2 * h)
+        return {"inside_fraction": float((s < 0).float().mean().item()),
+                "abs_s_p10_p50_p90": [float(s.abs().quantile(q).item()) for q in (0.1, 0.5, 0.9)],
+                "slope_along_ray_p10_p50_p90": [float(slope.quantile(q).item()) for q in (0.1, 0.5, 0.9)],
+                "slope_below_minus2_fraction": float((slope <= -2).float().mean().item()),
+                "exact_cast_hit_fraction": float((hg[u] > 0).float().mean().item())}
+
+    def stats(ms, res_t, hg, m=n):
         t, hit, steps = res_t
         st = steps.float()
         hist = torch.bincount(steps.long().clamp(0, 128), minlength=129).cpu().numpy()
-        r = {"ms": ms, "rays_per_s": n / (ms * 1e-3), "mean_steps": float(st.mean().item()),
+        r = {"ms": ms, "rays_per_s": m / (ms * 1e-3), "mean_steps": float(st.mean().item()),
              "p50_steps": float(st.median().item()), "unconverged_fraction": float((steps >= 128).float().mean().item()),
+             "stopped_at_first_evaluation_fraction": float(((steps == 1) & (hit > 0)).float().mean().item()),
              "hit_rate": float(hit.float().mean().item()),
-             "hit_agreement_vs_exact_cast": float((hit == hg).float().mean().item()),
+             "hit_agreement_vs_exact_cast": float((hit == hg[:m]).float().mean().item()),
              "steps_histogram": {f"{edges[i]}-{edges[i + 1] - 1}": int(hist[edges[i]:edges[i + 1]].sum())
                                  for i in range(len(edges) - 1)}}
-        for p in ("fp32", "bf16", "fp8"):
-            msp = prec.get(p, {}).get("ms")
-            if msp:
-                r[f"speedup_vs_ddf_{p}"] = ms / msp
+        if m == n:
+            for p in ("fp32", "bf16", "fp8"):
+                msp = prec.get(p, {}).get("ms")
+                if msp:
+                    r[f"speedup_vs_ddf_{p}"] = ms / msp
         return r
 
     res = {"sdf": "12x1024 SDF MLP (L=10, 63 features) fitted to the scene's distance bound", "fit": fit,
            "max_steps": 128, "t_max": 6.0, "precision": "fp32", "pool": {}}
     wsp = torch.empty(256, dtype=torch.uint8, device=dev)
-    for eps in (1e-2, 1e-3, 1e-4):
-        run = lambda: ddf.sphere_trace(desc, "fp32", packed, rays, 128, eps, 6.0, ws=wsp, pool=True)
+    for eps, (lift, r, hg) in sets.items():
+        run = lambda: ddf.sphere_trace(desc, "fp32", packed, r, 128, eps, 6.0, ws=wsp, pool=True)
         ms = timer.time(run, 1)
-        res["pool"][f"{eps:g}"] = stats(ms, run())
+        got = run()
+        res["pool"][f"{eps:g}"] = dict(origin_lift=lift, **stats(ms, got, hg))
+        if eps == 1e-4:
+            res["pool"][f"{eps:g}"]["unconverged_rays"] = stuck(r, hg, got[0], got[2])
+    lift, rays, hg = sets[1e-4]
     ws = torch.empty(int(ddf.lib().sdf_trace_workspace_bytes(n)), dtype=torch.uint8, device=dev)
     run = lambda: ddf.sphere_trace(desc, "fp32", packed, rays, 128, 1e-4, 6.0, ws=ws)
     ms = timer.time(run, 1)
-    res["step_synchronous_1e-4"] = stats(ms, run())
+    res["step_synchronous_1e-4"] = stats(ms, run(), hg)
     run = lambda: ddf.sphere_trace(desc, "bf16", packed_bf16, rays, 128, 1e-4, 6.0, ws=wsp, pool=True)
     ms16 = timer.time(run, 1)
-    r16 = stats(ms16, run())
+    r16 = stats(ms16, run(), hg)
     res["bf16_pool_1e-4"] = {k: v for k, v in r16.items() if k != "steps_histogram"}
-    return res
+
+    by_n = {}
+    for m in (1000, 10000, 100000):
+        row = {}
+        tq = torch.empty(m, dtype=torch.float32, device=dev)
+        xq = torch.empty(m, dtype=torch.float32, device=dev)
+        rq = shadow.rays[:, :m].contiguous()
+        for p in ("fp32", "bf16"):
+            pk, dc = shadow.packed(p), ddf.desc_c(shadow.desc, p)
+            for _ in range(3):
+                ddf.query_into(dc, pk, rq, tq, xq)
+            torch.cuda.synchronize()
+            row[f"ddf_{p}_ms"] = timer.time(lambda: ddf.query_into(dc, pk, rq, tq, xq), 20)
+        for eps in (1e-3, 1e-4):
+            lift, r, hg = sets[eps]
+            r = r[:, :m].contiguous()
+            run = lambda: ddf.sphere_trace(desc, "fp32", packed, r, 128, eps, 6.0, ws=wsp, pool=True)
+            run()
+            ms = timer.time(run, 3)
+            s = {k: v for k, v in stats(ms, run(), hg, m).items() if k not in ("steps_histogram", "rays_per_s")}
+            s.update({f"speedup_vs_ddf_{p}": ms / row[f"ddf_{p}_ms"] for p in ("fp32", "bf16")})
+            row[f"trace_{eps:g}"] = s
+        by_n[str(m)] = row
+    res["by_ray_count"] = by_n
+    host = {eps: (lift, r[:, ::128].cpu().numpy()) for eps, (lift, r, hg) in sets.items()}
+    return res, host
+
+
+def trace_oracle_stats(scene, host_sets, report, max_steps=128, t_max=6.0):
+    """cpu leg, the trace baseline's yardstick: the float64 oracle sphere-traces the scene's
+    analytic distance bound itself (the function the SDF MLP was fitted to) along every 128th
+    ray of each threshold's traced set: evaluations per ray, unconverged share, rays stopping
+    at their first evaluation and hits against exact casting."""
+    from oracle import geometry as G
+    out = {}
+    for eps, (lift, r) in host_sets.items():
+        o = r[0:3].T.astype(np.float64)
+        d = r[3:6].T.astype(np.float64)
+        t0 = time.perf_counter()
+        _, hg = G.intersect(scene, o, d)[:2]
+        _, hit, steps, _ = G.sphere_trace(lambda p: G.sdf(scene, p), o, d, max_steps, eps, t_max)
+        out[f"{eps:g}"] = {"rays": int(len(o)), "origin_lift": lift, "mean_steps": float(steps.mean()),
+                           "unconverged_fraction": float((steps >= max_steps).mean()),
+                           "stopped_at_first_evaluation_fraction": float(((steps == 1) & hit).mean()),
+                           "hit_agreement_vs_exact_cast": float((hit == hg).mean()),
+                           "oracle_s": time.perf_counter() - t0}
+    report["exact_bound_float64"] = out
 
 
 if __name__ == "__main__":

@@ -291,10 +291,11 @@ def surface_points(scene: Scene, n: int, seed: int):
     return np.concatenate(ps)[:n], np.concatenate(ns)[:n]
 
 
-def shadow_rays(scene: Scene, n: int, seed: int, light=LIGHT_POS) -> np.ndarray:
-    """Surface point lifted by NORMAL_OFFSET along its normal, pointing at the light."""
+def shadow_rays(scene: Scene, n: int, seed: int, light=LIGHT_POS, offset=NORMAL_OFFSET) -> np.ndarray:
+    """Surface point lifted by `offset` (default NORMAL_OFFSET) along its normal, pointing at
+    the light."""
     p, nrm = surface_points(scene, n, seed)
-    o = p + NORMAL_OFFSET * nrm
+    o = p + offset * nrm
     return _soa(o, np.asarray(light)[None] - o)
 
 
@@ -378,6 +379,15 @@ def sdf_train_points(scene: Scene, n: int, seed: int, sigma: float = 0.05) -> np
     p, _ = surface_points(scene, n - h, seed + 1)
     p = p + rng.standard_normal(p.shape) * sigma
     return np.ascontiguousarray(np.concatenate([u, p]).T.astype(np.float32))
+
+
+def sdf_fit_points(scene: Scene, n: int, seed: int) -> np.ndarray:
+    """SDF fitting samples with a tighter band at the surface, float32 [3, N]: half uniform in
+    the box, a quarter displaced from the surface by N(0, 0.05^2), a quarter by N(0, 0.005^2)."""
+    h = n // 2
+    a = sdf_train_points(scene, h, seed, sigma=0.05)
+    b = sdf_train_points(scene, n - h, seed + 5000, sigma=0.005)
+    return np.ascontiguousarray(np.concatenate([a, b], axis=1))
 
 
 def sdf_points(n: int, seed: int) -> np.ndarray:
