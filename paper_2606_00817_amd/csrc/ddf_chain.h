@@ -77,53 +77,80 @@ struct Chain {
     }
   }
 
+  // One quarter of the k loop, blocks k .. k + 3: before each block's products, the ring
+  // load three blocks ahead and the LDS read of the next block's activations.  TAIL = false:
+  // on a layer's last quarter these fall past the end (the weight loads are bounds-checked by
+  // the buffer resource and return zeros, the LDS read stays in the tile's padding; neither
+  // is used); TAIL = true, the layer's last quarter: its ring loads fetch blocks 0..2 of the
+  // next layer (resource rsn, offsets basen + t tstriden) instead, and nothing is read past
+  // the end.
+  template <bool TRANS, bool TAIL>
+  static __device__ inline void quarter(f32x16 (&acc)[RT][NT], AFrag (&a0)[RT], AFrag (&a1)[RT], const E* xrow,
+                                        __amdgpu_buffer_rsrc_t rs, int voff, int base, int tstride, int k, Ring& r,
+                                        __amdgpu_buffer_rsrc_t rsn, int basen, int tstriden) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) r.b3[t] = ld(rs, voff, base, tstride, t, k + 3);
+    load_a(a1, xrow, k + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_all<TRANS>(acc, a0, r.b0);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      r.b0[t] = TAIL ? ld(rsn, voff, basen, tstriden, t, 0) : ld(rs, voff, base, tstride, t, k + 4);
+    load_a(a0, xrow, k + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_all<TRANS>(acc, a1, r.b1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      r.b1[t] = TAIL ? ld(rsn, voff, basen, tstriden, t, 1) : ld(rs, voff, base, tstride, t, k + 5);
+    load_a(a1, xrow, k + 3);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_all<TRANS>(acc, a0, r.b2);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+      r.b2[t] = TAIL ? ld(rsn, voff, basen, tstriden, t, 2) : ld(rs, voff, base, tstride, t, k + 6);
+    if (!TAIL) load_a(a0, xrow, k + 4);
+    __builtin_amdgcn_sched_barrier(0);
+    mma_all<TRANS>(acc, a1, r.b3);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
   // TRANS = false: acc[rt][t] = X_tile * W_tile^T (rows rays, columns neurons).
   // TRANS = true : acc[rt][t] = W_tile * X_tile^T (rows neurons, columns rays): the same
   //   operand blocks with their matrix-core roles swapped, so that each lane ends up with 4
   //   consecutive neurons of one ray per register group.
   // acc[rt][t] accumulates over the wave's neuron tile (nt0 + t) and all K inputs.  The weight
   // blocks of one layer are read through a buffer resource three blocks ahead in a ring of
-  // four (the first three already issued by preload); KB is a multiple of 4, and the loads
-  // past the end of the layer are bounds-checked by the buffer resource (they return zeros,
-  // never used).  KBC > 0 fixes KB at compile time (hidden layers): the k loop is then fully
-  // unrolled.
-  template <int KBC, bool TRANS = false>
+  // four (the first three already issued by preload); KB is a multiple of 4.  The last
+  // quarter has no blocks of this layer left to fetch: with NEXT its ring loads take blocks
+  // 0..2 of the layer Wn (KBn blocks per tile) that follows, leaving the ring as preload(Wn)
+  // would, issued during this layer's last products and with no address-unit cycles spent on
+  // blocks past the end of the layer.  Without NEXT (the training kernels, whose epilogues
+  // have no registers to spare for a ring held across them) the loop stays uniform and its
+  // last loads fall past the end.  KBC > 0 fixes KB at compile time (hidden layers): the k
+  // loop is then fully unrolled.
+  template <int KBC, bool TRANS = false, bool NEXT = false>
   static __device__ inline void gemm(f32x16 (&acc)[RT][NT], const E* X, const void* W, int KB_rt,
-                                     int nt0, int lane, Ring& r) {
+                                     int nt0, int lane, Ring& r, const void* Wn = nullptr, int KBn = 0) {
     const int KB = KBC > 0 ? KBC : KB_rt;
     const __amdgpu_buffer_rsrc_t rs = rsrc(W, KB);
     const int voff = lane * 16, base = nt0 * KB * 1024, tstride = KB * 1024;
+    const __amdgpu_buffer_rsrc_t rsn = rsrc(NEXT ? Wn : W, NEXT ? KBn : KB);
+    const int basen = nt0 * KBn * 1024, tstriden = KBn * 1024;
     const E* xrow = X + (lane & 31) * LDX + (P::KBLK / 2) * (lane >> 5);
     AFrag a0[RT], a1[RT];
     load_a(a0, xrow, 0);
+    if constexpr (!NEXT) {
 #pragma unroll (KBC > 0 ? KBC / 4 : 1)
-    for (int k = 0; k < KB; k += 4) {
-      // each quarter: issue the weight loads three blocks ahead and the LDS read of the next
-      // block's activations, then the matrix products of this block
-#pragma unroll
-      for (int t = 0; t < NT; ++t) r.b3[t] = ld(rs, voff, base, tstride, t, k + 3);
-      load_a(a1, xrow, k + 1);
-      __builtin_amdgcn_sched_barrier(0);
-      mma_all<TRANS>(acc, a0, r.b0);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) r.b0[t] = ld(rs, voff, base, tstride, t, k + 4);
-      load_a(a0, xrow, k + 2);
-      __builtin_amdgcn_sched_barrier(0);
-      mma_all<TRANS>(acc, a1, r.b1);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) r.b1[t] = ld(rs, voff, base, tstride, t, k + 5);
-      load_a(a1, xrow, k + 3);
-      __builtin_amdgcn_sched_barrier(0);
-      mma_all<TRANS>(acc, a0, r.b2);
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) r.b2[t] = ld(rs, voff, base, tstride, t, k + 6);
-      load_a(a0, xrow, k + 4);   // one block past the end on the last pass: inside the row padding
-      __builtin_amdgcn_sched_barrier(0);
-      mma_all<TRANS>(acc, a1, r.b3);
-      __builtin_amdgcn_sched_barrier(0);
+      for (int k = 0; k < KB; k += 4)
+        quarter<TRANS, false>(acc, a0, a1, xrow, rs, voff, base, tstride, k, r, rsn, basen, tstriden);
+    } else {
+#pragma unroll (KBC > 4 ? KBC / 4 - 1 : 1)
+      for (int k = 0; k < KB - 4; k += 4)
+        quarter<TRANS, false>(acc, a0, a1, xrow, rs, voff, base, tstride, k, r, rsn, basen, tstriden);
+      quarter<TRANS, true>(acc, a0, a1, xrow, rs, voff, base, tstride, KB - 4, r, rsn, basen, tstriden);
     }
   }
 

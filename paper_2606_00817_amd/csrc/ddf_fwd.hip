@@ -146,21 +146,24 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd_kernel(FwdArgs a) {
       for (int j = 0; j < kBL; ++j)
         if (j * 64 + lane < kNW) bv[j] = bl[j * 64 + lane];
     }
-    // query modes issue a layer's first weight blocks before the previous layer's epilogue
-    // (they do not depend on its output); the training epilogue has no registers to spare
+    // query modes fetch a layer's first weight blocks during the previous layer's last
+    // products (they do not depend on its output; after the last layer a harmless re-read of
+    // its own first blocks); the training epilogue has no registers to spare for them
+    const bool more = l + 1 < a.l_end;
+    const void* Wn = more ? a.packed + a.lay.w_off[l + 1] : W;
+    const int KBn = more ? WIDTH / P::KBLK : K / P::KBLK;
     if (l == 0) {
       C::preload(ring, W, K / P::KBLK, nt0, lane);
-      C::template gemm<0, kTrans>(acc, X, W, K / P::KBLK, nt0, lane, ring);
+      C::template gemm<0, kTrans, kTrans>(acc, X, W, K / P::KBLK, nt0, lane, ring, Wn, KBn);
     } else {
       if (!kTrans) C::preload(ring, W, WIDTH / P::KBLK, nt0, lane);
-      C::template gemm<WIDTH / P::KBLK, kTrans>(acc, X, W, K / P::KBLK, nt0, lane, ring);
+      C::template gemm<WIDTH / P::KBLK, kTrans, kTrans>(acc, X, W, K / P::KBLK, nt0, lane, ring, Wn, KBn);
     }
     if constexpr (kTrans) {
 #pragma unroll
       for (int j = 0; j < kBL; ++j)
         if (j * 64 + lane < kNW) bsm[nt0 * 32 + j * 64 + lane] = bv[j];
     }
-    if (kTrans && l + 1 < a.l_end) C::preload(ring, a.packed + a.lay.w_off[l + 1], WIDTH / P::KBLK, nt0, lane);
     __syncthreads();   // every wave is done reading X
     if constexpr (kTrans) {
       epilogue_t<P, WIDTH, MODE, WAVES>(a, acc, X, headp, bsm, l, ray0, n_act, nt0, lane, wave);
@@ -380,16 +383,20 @@ __global__ __launch_bounds__(WAVES * 64, 1) void pool_trace_kernel(FwdArgs a) {
 #pragma unroll
       for (int j = 0; j < kBL; ++j)
         if (j * 64 + lane < kNW) bv[j] = bl[j * 64 + lane];
+      // the next layer's first blocks come with this layer's last products (after the last
+      // layer a harmless re-read of its own first blocks)
+      const bool more = l + 1 < a.n_hidden;
+      const void* Wn = more ? a.packed + a.lay.w_off[l + 1] : W;
+      const int KBn = more ? WIDTH / P::KBLK : K / P::KBLK;
       if (l == 0) {
         C::preload(ring, W, K / P::KBLK, nt0, lane);
-        C::template gemm<0, true>(acc, X, W, K / P::KBLK, nt0, lane, ring);
+        C::template gemm<0, true, true>(acc, X, W, K / P::KBLK, nt0, lane, ring, Wn, KBn);
       } else {
-        C::template gemm<WIDTH / P::KBLK, true>(acc, X, W, K / P::KBLK, nt0, lane, ring);
+        C::template gemm<WIDTH / P::KBLK, true, true>(acc, X, W, K / P::KBLK, nt0, lane, ring, Wn, KBn);
       }
 #pragma unroll
       for (int j = 0; j < kBL; ++j)
         if (j * 64 + lane < kNW) bsm[nt0 * 32 + j * 64 + lane] = bv[j];
-      if (l + 1 < a.n_hidden) C::preload(ring, a.packed + a.lay.w_off[l + 1], WIDTH / P::KBLK, nt0, lane);
       __syncthreads();
       epilogue_t<P, WIDTH, kModePool, WAVES>(a, acc, X, headp, bsm, l, 0, M, nt0, lane, wave);
     }
