@@ -270,6 +270,14 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const int tile0 = wave * NTW + p * NTP;
+      // issue priority: pass 0's products above pass 1's, both above the epilogues.  Of the
+      // two waves of a SIMD, the one that takes the matrix cores first (the older) would
+      // otherwise also take them back for its pass 1 while the other is still in its pass 0,
+      // leaving the other's epilogues with nothing to overlap; this way the waves alternate.
+      if (p == 0)
+        __builtin_amdgcn_s_setprio(3);
+      else
+        __builtin_amdgcn_s_setprio(2);
       f32x16 acc[kRT8][NTP];
 #pragma unroll
       for (int rt = 0; rt < kRT8; ++rt)
@@ -288,6 +296,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
       // before the epilogue (after the last layer, a harmless re-read of its own blocks)
       if (WAVES == 8 && p == 1)
         preload8<NTP, WIDTH / 64>(ring, a.packed + a.lay.w_off[last ? l : l + 1], wave * NTW, lane, WIDTH);
+      __builtin_amdgcn_s_setprio(0);
       if (p == 0) {
         const int el = fresh_lane();
 #pragma unroll
