@@ -303,7 +303,9 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
         for (int j = 0; j < kBL; ++j)
           if (j * 64 + el < kNW) bsm[wave * kNW + j * 64 + el] = bv[j];
       }
-      if (p == 1) __syncthreads();   // every wave is done reading this layer's input
+      // the heads read no tile; a layer feeding another writes the tile only after its pass-1
+      // outputs are rounded (below), so that a wave waiting for the others has that work done
+      if (p == 1 && last) __syncthreads();
       const int el = fresh_lane();
       // the two epilogues are separate uniform branches, so that neither carries the
       // other's tests inside its unrolled loops
@@ -336,14 +338,7 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
           }
         }
       } else {
-        if (p == 1) {
-#pragma unroll
-          for (int rt = 0; rt < kRT8; ++rt)
-#pragma unroll
-            for (int t = 0; t < NTP; ++t)
-              *reinterpret_cast<i32x4*>(X + (rt * 32 + (el & 31)) * LDX + (wave * NTW + t) * 32 + 16 * (el >> 5)) =
-                  i32x4{(int)hold[rt][t][0], (int)hold[rt][t][1], (int)hold[rt][t][2], (int)hold[rt][t][3]};
-        }
+        uint32_t hold1[kRT8][NTP][4];   // pass 1's rounded outputs, until the barrier
 #pragma unroll
         for (int t = 0; t < NTP; ++t) {
           const int nb = (tile0 + t) * 32 + 4 * (el >> 5);
@@ -368,13 +363,28 @@ __global__ __launch_bounds__(WAVES * 64, 1) void fwd8_kernel(FwdArgs a) {
 #pragma unroll
           for (int rt = 0; rt < kRT8; ++rt) {
             const i32x4 v = regroup16(w[rt]);
-            if (p == 0) {
 #pragma unroll
-              for (int q = 0; q < 4; ++q) hold[rt][t][q] = (uint32_t)v[q];
-            } else
-              *reinterpret_cast<i32x4*>(X + (rt * 32 + (el & 31)) * LDX + (tile0 + t) * 32 + 16 * (el >> 5)) = v;
+            for (int q = 0; q < 4; ++q) {
+              if (p == 0)
+                hold[rt][t][q] = (uint32_t)v[q];
+              else
+                hold1[rt][t][q] = (uint32_t)v[q];
+            }
           }
           __builtin_amdgcn_sched_barrier(0);
+        }
+        if (p == 1) {
+          __syncthreads();   // every wave is done reading this layer's input
+#pragma unroll
+          for (int rt = 0; rt < kRT8; ++rt)
+#pragma unroll
+            for (int t = 0; t < NTP; ++t) {
+              uint8_t* row = X + (rt * 32 + (el & 31)) * LDX + 16 * (el >> 5);
+              *reinterpret_cast<i32x4*>(row + (wave * NTW + t) * 32) =
+                  i32x4{(int)hold[rt][t][0], (int)hold[rt][t][1], (int)hold[rt][t][2], (int)hold[rt][t][3]};
+              *reinterpret_cast<i32x4*>(row + (wave * NTW + NTP + t) * 32) =
+                  i32x4{(int)hold1[rt][t][0], (int)hold1[rt][t][1], (int)hold1[rt][t][2], (int)hold1[rt][t][3]};
+            }
         }
       }
     }
