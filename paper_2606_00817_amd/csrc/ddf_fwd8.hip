@@ -159,7 +159,7 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc8(const void* W, int width) {
 }
 
 // Stages of the streamed product's weight ring.
-constexpr int kS8 = 3;
+constexpr int kS8 = 2;
 
 // First kS8 - 1 stages of an e4m3 layer's weight ring (issued ahead of time, before the
 // previous pass's epilogue: the weights do not depend on its output).
@@ -172,9 +172,10 @@ __device__ inline void preload8(i32x8 (&b)[kS8][NTP], const void* W, int tile0, 
     for (int t = 0; t < NTP; ++t) b[st][t] = ld8<KB>(rs, lane * 32, tile0 * KB * 2048, t, st);
 }
 
-// The same product with the activation operand streamed one 32-ray tile at a time (the
-// next tile's LDS read overlaps the current tile's products): fewer registers, for the
-// 8-wave layout where two waves share a SIMD's register file.  The ring's first kS8 - 1
+// The same product with the activation operand streamed one 32-ray tile at a time (the LDS
+// read of the tile two ahead overlaps the current tile's products) and the weight ring one k
+// step ahead: fewer registers, for the 8-wave layout where two waves share a SIMD's register
+// file.  The ring's first kS8 - 1
 // stages come from preload8.
 template <int NTP, int LDX, int KB>
 __device__ inline void gemm_f8_stream(f32x16 (&acc)[kRT8][NTP], const uint8_t* X, const void* W, int tile0,
@@ -183,23 +184,23 @@ __device__ inline void gemm_f8_stream(f32x16 (&acc)[kRT8][NTP], const uint8_t* X
   const int voff = lane * 32;
   const int base = tile0 * KB * 2048;
   const uint8_t* xrow = X + (lane & 31) * LDX + 32 * (lane >> 5);
-  i32x8 av[2];
+  // the activation operand two 32-ray tiles ahead, in a rotation of three
+  i32x8 av[3];
   av[0] = lds_a8(xrow);
+  av[1] = lds_a8(xrow + 32 * LDX);
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
 #pragma unroll
     for (int t = 0; t < NTP; ++t) b[(k + kS8 - 1) % kS8][t] = ld8<KB>(rs, voff, base, t, k + kS8 - 1);
 #pragma unroll
     for (int rt = 0; rt < kRT8; ++rt) {
-      const int i = k * kRT8 + rt;            // running tile index: parity picks the buffer
-      if (rt + 1 < kRT8)
-        av[(i + 1) & 1] = lds_a8(xrow + (rt + 1) * 32 * LDX + k * 64);
-      else if (k + 1 < KB)
-        av[(i + 1) & 1] = lds_a8(xrow + (k + 1) * 64);
+      const int i = k * kRT8 + rt;            // running tile index: i mod 3 picks the buffer
+      const int rt2 = (rt + 2) % kRT8, k2 = k + (rt + 2) / kRT8;
+      if (k2 < KB) av[(i + 2) % 3] = lds_a8(xrow + rt2 * 32 * LDX + k2 * 64);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < NTP; ++t)
-        acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(b[k % kS8][t], av[i & 1], acc[rt][t], 0, 0, 0,
+        acc[rt][t] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(b[k % kS8][t], av[i % 3], acc[rt][t], 0, 0, 0,
                                                                      127, 0, 127);
       __builtin_amdgcn_sched_barrier(0);
     }
