@@ -175,8 +175,7 @@ __device__ inline void preload8(i32x8 (&b)[kS8][NTP], const void* W, int tile0, 
 // The same product with the activation operand streamed one 32-ray tile at a time (the LDS
 // read of the tile two ahead overlaps the current tile's products) and the weight ring one k
 // step ahead: fewer registers, for the 8-wave layout where two waves share a SIMD's register
-// file.  The ring's first kS8 - 1
-// stages come from preload8.
+// file.  The ring's first kS8 - 1 stages come from preload8.
 template <int NTP, int LDX, int KB>
 __device__ inline void gemm_f8_stream(f32x16 (&acc)[kRT8][NTP], const uint8_t* X, const void* W, int tile0,
                                       int lane, int width, i32x8 (&b)[kS8][NTP]) {
