@@ -46,7 +46,15 @@ __global__ __launch_bounds__(64 * kSplitWaves, 1) void split_layer_kernel(SplitA
   __shared__ float hsum[kSplitWaves][M][2];
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int64_t ray0 = (int64_t)blockIdx.x * M;
+  // Workgroups go to the 8 XCDs in turn (id mod 8); the neuron groups of one ray tile take
+  // consecutive turns on the same XCD, so that they read the tile's input through one L2 at
+  // about the same time: the input is fetched past the L2 once, not once per group.
+  constexpr int G = WIDTH / kSplitNeurons;            // neuron groups per ray tile
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int64_t tile = (int64_t)(slot / G) * 8 + xcd;
+  const int group = slot % G;
+  if (tile * M >= a.R) return;                        // the grid is rounded up to 8 tiles
+  const int64_t ray0 = tile * M;
   const int l = a.layer;
 
   if (l == 0) {
@@ -75,7 +83,7 @@ __global__ __launch_bounds__(64 * kSplitWaves, 1) void split_layer_kernel(SplitA
   }
   __syncthreads();
 
-  const int nt0 = blockIdx.y * kSplitWaves + wave;   // this wave's neuron tile
+  const int nt0 = group * kSplitWaves + wave;   // this wave's neuron tile
   const int K = l == 0 ? a.f.lay.k1 : WIDTH;
   const void* W = a.f.packed + a.f.lay.w_off[l];
   f32x16 acc[RT][1];
@@ -138,7 +146,7 @@ __global__ __launch_bounds__(64 * kSplitWaves, 1) void split_layer_kernel(SplitA
       float z0 = 0.f, z1 = 0.f;
 #pragma unroll
       for (int w = 0; w < kSplitWaves; ++w) { z0 += hsum[w][r][0]; z1 += hsum[w][r][1]; }
-      float* dst = a.part + ((int64_t)blockIdx.y * a.R + ray0 + r) * 2;
+      float* dst = a.part + ((int64_t)group * a.R + ray0 + r) * 2;
       dst[0] = z0;
       dst[1] = z1;
     }
@@ -176,7 +184,8 @@ SplitWs split_ws(const ddf_net_desc& d, int64_t n) {
 
 template <int WIDTH>
 hipError_t launch_split(const SplitArgs& a, hipStream_t st) {
-  const dim3 grid((unsigned)(a.R / 64), (unsigned)(WIDTH / kSplitNeurons));
+  const int64_t tiles8 = (a.R / 64 + 7) / 8 * 8;   // ray tiles rounded up to the 8 XCDs
+  const dim3 grid((unsigned)(tiles8 * (WIDTH / kSplitNeurons)));
   hipLaunchKernelGGL((split_layer_kernel<WIDTH>), grid, dim3(64 * kSplitWaves), 0, st, a);
   return hipGetLastError();
 }
