@@ -102,6 +102,20 @@ __global__ void pack_layer_kernel(PackArgs a, int with_transposed) {
     const float* s = reinterpret_cast<const float*>(a.packed + a.lay.scale_off);
     qs = 1.f / s[4 * l + kScaleW];     // exact: a power of two
   }
+  if (!first && !transposed && eb == 2) {
+    // bf16 hidden layer in the master's orientation: the lane's 8 consecutive inputs are two
+    // 16-byte loads (row n, columns kbase .. kbase + 7), not 8 scalar ones
+    const f32x4* src = reinterpret_cast<const f32x4*>(W + (int64_t)n * fan_in + kbase);
+    const f32x4 v0 = src[0], v1 = src[1];
+    bf16x8 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      o[j] = to_bf16(v0[j]);
+      o[4 + j] = to_bf16(v1[j]);
+    }
+    *reinterpret_cast<bf16x8*>(dst) = o;
+    return;
+  }
   // the lane's bytes are gathered in registers and leave as 16-byte stores (per * eb is 16
   // or 32: fp32 8 x 4, bf16 8 x 2, e4m3 32 x 1, layer-1 bf16 8 x 2)
   i32x4 out[2] = {};
