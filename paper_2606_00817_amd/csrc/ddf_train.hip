@@ -683,11 +683,17 @@ __global__ void head_grad_partial_kernel(const E* Hn, const float* dzt, const fl
     for (int64_t rb = b0 + grp; rb < b1; rb += 8) {
       const V4<E> h0 = *reinterpret_cast<const V4<E>*>(Hn + (rb * W + j) * 8);
       const V4<E> h1 = *reinterpret_cast<const V4<E>*>(Hn + (rb * W + j) * 8 + 4);
+      // the block's 8 logit gradients of each head as two 16-byte loads (the same for every
+      // lane: R is a multiple of 64, so rows rb 8 .. rb 8 + 7 exist and are 32-byte aligned)
+      const f32x4 t0 = *reinterpret_cast<const f32x4*>(dzt + rb * 8);
+      const f32x4 t1 = *reinterpret_cast<const f32x4*>(dzt + rb * 8 + 4);
+      const f32x4 x0 = *reinterpret_cast<const f32x4*>(dzx + rb * 8);
+      const f32x4 x1 = *reinterpret_cast<const f32x4*>(dzx + rb * 8 + 4);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const float hv = (float)(q < 4 ? h0[q] : h1[q - 4]);
-        kahan_add(s0, c0, dzt[rb * 8 + q] * hv);
-        kahan_add(s1, c1, dzx[rb * 8 + q] * hv);
+        kahan_add(s0, c0, (q < 4 ? t0[q] : t1[q - 4]) * hv);
+        kahan_add(s1, c1, (q < 4 ? x0[q] : x1[q - 4]) * hv);
       }
     }
   } else {
