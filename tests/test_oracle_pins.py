@@ -528,3 +528,26 @@ def test_shift_rays_targets_match_exact_casting():
     assert not sh0.any() and np.array_equal(ro0, rays.astype(np.float64))
     _, _, _, _, shm = O.shift_rays(rays, t32, np.zeros(n, np.uint8), u, 1.0)
     assert not shm.any()
+
+
+def test_lifted_shadow_origins_sit_at_the_offset():
+    """The trace leg lifts shadow-ray origins past each hit threshold: on a sphere-only scene
+    (where the oracle's distance is exact) an origin lifted by `offset` along the outward
+    normal lies `offset` from the union surface, unless another sphere is nearer; the
+    fitting samples keep half their points uniform in the box and half near the surface."""
+    sc = I.scene_spheres(16, 5)
+    for off in (1e-3, 2e-3, 2e-2):
+        r = I.shadow_rays(sc, 2000, 9, offset=off).astype(np.float64)
+        s = G.sdf(sc, r[0:3].T)
+        close = np.abs(s - off) < 1e-5
+        assert close.mean() > 0.95, (off, close.mean())
+        assert np.all(s[~close] < off)          # only a nearer sphere can make it differ
+        d = r[3:6].T
+        assert np.allclose(np.linalg.norm(d, axis=1), 1.0, atol=1e-6)
+    p = I.sdf_fit_points(sc, 4000, 3).astype(np.float64)
+    s = np.abs(G.sdf(sc, p.T))
+    assert p.shape == (3, 4000)
+    assert np.all(np.abs(p) <= I.BOX_HALF + 0.2)
+    # [uniform | N(0, 0.05^2) band | uniform | N(0, 0.005^2) band], 1000 points each
+    wide, tight = s[1000:2000], s[3000:4000]
+    assert np.median(tight) < 0.01 < np.median(wide) < 0.1 < np.median(s[:1000])
